@@ -1,0 +1,168 @@
+"""Benchmark: Yee FDTD leapfrog on a 512^3 PEC cavity with spherical inclusions, FP32.
+
+One benchmark "step" is one leapfrog step (update H, then update E, PEC walls)
+of the whole 512^3 cavity, i.e. one pass of the full hot path over one state.
+Inputs (fields, coefficients) are resident in HBM before the timed region.
+
+Prints one JSON line with the throughput in Gcell-updates/s, the roofline of
+the dominant kernel (algorithmic bytes per launch / average launch duration,
+timed with events on the stream the kernels run on) and the FP64 CPU oracle
+timed on the host on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def algorithmic_bytes_per_cell_step(kernel: str, ce_arrays: bool, ch_arrays: bool, esz: int = 4) -> float:
+    """Bytes the method must move per cell and step for one schedule.
+
+    fused / slab: the six components read once and written once (12 words)
+    plus one word per per-node coefficient array. plain: sweep 1 reads E and
+    reads/writes H (9 words + Ch arrays), sweep 2 reads H and reads/writes E
+    (9 words + Ce arrays).
+    """
+    coef = (3 if ce_arrays else 0) + (3 if ch_arrays else 0)
+    if kernel == "plain":
+        return (18 + coef) * esz
+    return (12 + coef) * esz
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=512, help="cells per axis")
+    ap.add_argument("--kernel", default="auto")
+    ap.add_argument("--tb-steps", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the cavity would shard as z-slabs with one-plane halo exchanges)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import cavity_inputs as ci
+    from paper_2504_09118_amd import Solver
+
+    n = args.n
+    nx = ny = nz = n
+    dx, dt = 1.0, 0.5 / math.sqrt(3.0)
+    t0 = time.time()
+    eps = ci.sphere_eps(nx, ny, nz, seed=33)
+    e = ci.random_e(nx, ny, nz, seed=3, dtype=np.float32)
+    print(f"[bench] inputs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    torch.cuda.init()
+    stream = torch.cuda.Stream()  # default priority; the solver enqueues here and the events time it
+    s = Solver(nx, ny, nz, dx, dt, eps_r=eps, kernel=args.kernel, tb_steps=args.tb_steps, stream=stream)
+    s.set_fields(e)
+    q = s.query()
+    kernel = q["kernel"]
+    steps_per_launch = int(q["steps_per_sweep"])
+    if args.steps % steps_per_launch or args.warmup % steps_per_launch:
+        print("steps and warmup must be multiples of the steps per sweep", file=sys.stderr)
+        return 2
+    s.step(args.warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    print(f"[bench] kernel={kernel} warmup done", file=sys.stderr, flush=True)
+
+    sweeps0 = q["sweeps"]
+    sweeps_before = s.query()["sweeps"]
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    sweeps = s.query()["sweeps"] - sweeps_before
+    d = s.diag()
+    s.close()
+    del sweeps0
+
+    cells = nx * ny * nz
+    secs = ms / 1e3
+    gcells = cells * args.steps / secs / 1e9
+    launches_per_sweep = 2 if kernel == "plain" else 1
+    launches = sweeps * launches_per_sweep
+    avg_launch_s = secs / launches
+    b_cell = algorithmic_bytes_per_cell_step(kernel, q["ce_array"], q["ch_array"])
+    # bytes one launch must move: one sweep covers steps_per_launch steps but reads/writes the state once
+    bytes_per_launch = b_cell * cells / launches_per_sweep
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+
+    result = {
+        "metric": "Gcell-updates/s (512^3 FP32 PEC cavity, spherical eps inclusions)",
+        "value": round(gcells, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: 32 seeded spherical inclusions eps_r~U[1,4], E~U[-1,1] (SplitMix64), H=0",
+        "config": {"workload": f"box cavity {nx}x{ny}x{nz}, FP32 fields, per-node Ce from per-cell eps_r, "
+                               f"scalar Ch, Courant 0.5/sqrt(3)",
+                   "kernel": kernel, "steps_per_launch": steps_per_launch, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_cell_step": b_cell / steps_per_launch,
+                     "avg_launch_ms": round(avg_launch_s * 1e3, 5)},
+        "wall_s": round(wall, 4),
+        "energy_check": {"nonfinite": d["nonfinite"], "max_e_tan": d["max_e_tan"]},
+    }
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(e, eps, nx, ny, nz, dx, dt, args.cpu_steps)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def cpu_baseline(e32, eps, nx, ny, nz, dx, dt, steps):
+    """The FP64 oracle, as it stands, on the full 512^3 state for a few steps on the host cores."""
+    import numpy as np
+
+    import oracle
+
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    ce = oracle.coef_e(nx, ny, nz, dx, dt, eps)
+    ch = oracle.coef_h(nx, ny, nz, dx, dt)
+    fields = oracle.make_state([a.astype(np.float64) for a in e32])
+    t0 = time.perf_counter()
+    oracle.run(fields, ce, ch, steps)
+    secs = time.perf_counter() - t0
+    rate = nx * ny * nz * steps / secs / 1e9
+    return {"value": round(rate, 5), "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"full {nx}x{ny}x{nz} cavity, same inputs, {steps} leapfrog steps in FP64 "
+                      f"({secs:.1f}s)"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,202 @@
+/*
+ * fdtd.h -- C ABI of the MI355X (gfx950) Yee FDTD library, libfdtd.so.
+ *
+ * The library advances Maxwell's curl equations on a PEC box cavity with the
+ * Yee leapfrog (He, Andersson, Markidis, "Optimizing FDTD Solvers for
+ * Electromagnetics: A Compiler-Guided Approach with High-Level Tensor
+ * Abstractions", arXiv 2504.09118):
+ *   - Sec. 2.1, Eq. 2: the six component updates; E uses dt/eps, H uses
+ *     dt/mu, with the minus sign of Faraday's law as printed in Eq. 2.
+ *   - Sec. 2.2, full algorithm listing: each step updates H from the curl
+ *     of E, applies the H boundary, updates E from the curl of H, applies the
+ *     E boundary.
+ *   - Sec. 2.2, naive and slicing curl_Hx listings: forward differences of E
+ *     for H, staggered array extents.
+ *   - Fig. 1b caption and Sec. 4: PEC walls on a box cavity.
+ *
+ * Units: the caller chooses them; the library only uses dx, dt and the
+ * relative material values. With c = eps0 = mu0 = 1 the coefficients are
+ * Ce = dt/(eps_r dx) and Ch = dt/(mu_r dx).
+ *
+ * Host field layout (all set/get calls): each component is a dense
+ * x-fastest array, element (i, j, k) at i + X*(j + Y*k), with extents (X,Y,Z)
+ *   Ex (nx, ny+1, nz+1)   Ey (nx+1, ny, nz+1)   Ez (nx+1, ny+1, nz)
+ *   Hx (nx+1, ny, nz)     Hy (nx, ny+1, nz)     Hz (nx, ny, nz+1)
+ * (in NumPy terms a C-order array of shape (Z, Y, X) indexed [k, j, i]).
+ * The order of the six pointers in every array argument is Ex, Ey, Ez, Hx,
+ * Hy, Hz. The device layout is private to the library.
+ *
+ * Time levels (the algorithm listing's H-then-E order): after set_fields,
+ * E holds E^0 and H holds H^{-1/2}; after step(n) the state is E^n, H^{n-1/2}.
+ *
+ * Errors: every call returns an fdtd_status and never throws. On failure
+ * fdtd_last_error() returns a thread-local message. A handle whose device
+ * work failed enters an error state; later calls on it return FDTD_E_STATE
+ * (except fdtd_destroy).
+ *
+ * Threading: a handle is not thread-safe; different handles may be used from
+ * different threads on different streams.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_solver *fdtd_t;
+
+typedef enum {
+    FDTD_OK = 0,
+    FDTD_E_ARG = -1,          /* invalid argument (dims, dx, dt, NULL pointer, material value) */
+    FDTD_E_CFL = -2,          /* dt violates the Courant limit of the given medium */
+    FDTD_E_NOMEM = -3,        /* device memory or the caller's arena is too small */
+    FDTD_E_DEVICE = -4,       /* a HIP call or a kernel failed */
+    FDTD_E_STATE = -5,        /* NULL / destroyed / errored handle, or fields never set */
+    FDTD_E_UNSUPPORTED = -6   /* option combination not built */
+} fdtd_status;
+
+/* Element types of host or device buffers and of the device field storage. */
+typedef enum { FDTD_F64 = 0, FDTD_F32 = 1 } fdtd_dtype;
+
+/* Field indices in the six-pointer arrays. */
+enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ };
+
+/* Kernel schedules for fdtd_step (all give the same bits for the same storage type). */
+typedef enum {
+    FDTD_KERNEL_AUTO = 0,      /* the fastest built schedule for the storage type */
+    FDTD_KERNEL_PLAIN = 1,     /* two sweeps per step: update H, then update E, in place */
+    FDTD_KERNEL_FUSED = 2,     /* one z-marching sweep per step (H then E per plane) */
+    FDTD_KERNEL_SLAB = 3,      /* fused sweep with LDS-staged plane tiles */
+    FDTD_KERNEL_TEMPORAL = 4   /* tb_steps full steps per sweep (temporal blocking) */
+} fdtd_kernel;
+
+/*
+ * Per-cell materials, both x-fastest arrays of nx*ny*nz host doubles; NULL
+ * means 1 everywhere. The coefficient of an E node (a cell edge) uses the
+ * mean eps_r of the four cells sharing the edge, summed as ((a+b)+(c+d))/4;
+ * an H node (a face) the mean mu_r of its two cells. The means, divisions and
+ * the rounding to the storage type are done in FP64 on the device, once, at
+ * fdtd_create. NULL eps_r (mu_r) keeps a single scalar coefficient instead of
+ * per-node arrays.
+ */
+typedef struct {
+    const double *eps_r;
+    const double *mu_r;
+} fdtd_coef;
+
+typedef struct {
+    int storage;        /* fdtd_dtype of device fields: FDTD_F32 (default) or FDTD_F64 */
+    int kernel;         /* fdtd_kernel, default FDTD_KERNEL_AUTO */
+    int tb_steps;       /* steps per sweep for FDTD_KERNEL_TEMPORAL (0: library default) */
+    int device;         /* HIP device ordinal, default 0 */
+    void *stream;       /* hipStream_t to enqueue on; NULL: the library creates its own */
+    void *arena;        /* caller-owned device memory for all device state; NULL: hipMalloc */
+    size_t arena_bytes; /* size of arena in bytes (>= fdtd_required_bytes) */
+} fdtd_opts;
+
+/* Fill *opts with the defaults listed above. Returns FDTD_E_ARG for NULL. */
+int fdtd_opts_default(fdtd_opts *opts);
+
+/*
+ * Device bytes fdtd_create needs for these dims, materials and options (the
+ * arena size a caller must provide). coef and opts may be NULL (defaults).
+ * Returns FDTD_E_ARG for dims < 2 or NULL out.
+ */
+int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdtd_opts *opts,
+                        size_t *out);
+
+/*
+ * Create a solver for an nx*ny*nz-cell PEC cavity with cubic cells of size dx
+ * and time step dt, and enqueue the coefficient precompute on its stream.
+ * Fields start at zero.
+ * Checks: nx, ny, nz >= 2; dx, dt finite and > 0; every material value
+ * finite and > 0; the Courant limit dt*sqrt(3)/dx < sqrt(min eps_r * min mu_r)
+ * (FDTD_E_CFL); arena large enough (FDTD_E_NOMEM). Host arrays in coef are
+ * read during the call only. The arena, if given, is borrowed until
+ * fdtd_destroy and must stay allocated. *out is set only on FDTD_OK.
+ */
+int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *coef,
+                const fdtd_opts *opts, fdtd_t *out);
+
+/*
+ * Set the state to (E^0, H^{-1/2}) from six host arrays of type host_dtype
+ * (FDTD_F64 or FDTD_F32) in the host layout above. Values are rounded to the
+ * storage type (nearest even). Tangential E on the six walls is set to 0 (PEC)
+ * whatever the input holds. Resets the step counter to 0. Host pointers are
+ * read during the call only. Synchronous with respect to the host buffers.
+ */
+int fdtd_set_fields(fdtd_t h, const void *const host[6], int host_dtype);
+
+/* As fdtd_set_fields, from six device buffers (same layout); enqueued on the solver's stream. */
+int fdtd_set_fields_device(fdtd_t h, const void *const dev[6], int dev_dtype);
+
+/*
+ * Enqueue n >= 0 leapfrog steps (Sec. 2.2 algorithm listing: H update, H
+ * boundary, E update, E boundary). Asynchronous: returns after launching.
+ * Launch failures return FDTD_E_DEVICE at once; faults during execution
+ * surface at the next fdtd_sync / fdtd_get_fields.
+ */
+int fdtd_step(fdtd_t h, long long n);
+
+/*
+ * Copy the current state (E^n, H^{n-1/2}) into six host arrays of type
+ * host_dtype in the host layout above; waits for all enqueued work.
+ */
+int fdtd_get_fields(fdtd_t h, void *const host[6], int host_dtype);
+
+/* As fdtd_get_fields, into six device buffers; enqueued on the solver's stream (no wait). */
+int fdtd_get_fields_device(fdtd_t h, void *const dev[6], int dev_dtype);
+
+/*
+ * Copy the per-node coefficients into six host arrays of type host_dtype,
+ * laid out like the fields: Ce for Ex, Ey, Ez and Ch for Hx, Hy, Hz (0 on
+ * wall-tangential E and wall-normal H nodes, which never change). Values are
+ * the storage-type numbers the kernels use.
+ */
+int fdtd_get_coefs(fdtd_t h, void *const host[6], int host_dtype);
+
+/* Wait for all work enqueued on the solver's stream; reports deferred device faults. */
+int fdtd_sync(fdtd_t h);
+
+/* Number of leapfrog steps applied since the last set_fields (-1 for an invalid handle). */
+long long fdtd_steps_done(fdtd_t h);
+
+/* Diagnostics computed in FP64 on the device from the stored fields; waits. */
+enum {
+    FDTD_DIAG_ENERGY = 0,   /* W = sum E^2/Ce + sum H^{n-1/2} H^{n+1/2}/Ch (conserved exactly in exact arithmetic) */
+    FDTD_DIAG_SUM_E2 = 1,   /* sum of E^2 over all E nodes */
+    FDTD_DIAG_SUM_H2 = 2,   /* sum of H^2 over all H nodes */
+    FDTD_DIAG_MAX_DIVB = 3, /* max over cells of |div (H/Ch)| (wall-normal H counted as 0) */
+    FDTD_DIAG_MAX_ETAN = 4, /* max |tangential E| on the six walls (0 under PEC) */
+    FDTD_DIAG_NONFINITE = 5,/* number of non-finite field values */
+    FDTD_DIAG_N = 6
+};
+int fdtd_diag(fdtd_t h, double out[FDTD_DIAG_N]);
+
+/*
+ * Resolved configuration: out[0] kernel, out[1] steps per sweep, out[2]
+ * storage dtype, out[3] sweeps launched since create, out[4] per-node Ce (1/0),
+ * out[5] per-node Ch (1/0), out[6] padded x pitch, out[7] device bytes used.
+ */
+int fdtd_query(fdtd_t h, long long out[8]);
+
+/* The hipStream_t the solver enqueues on. */
+void *fdtd_stream(fdtd_t h);
+
+/* Release device memory the library allocated (not a caller arena) and the handle. */
+int fdtd_destroy(fdtd_t h);
+
+/* Static text for a status code. */
+const char *fdtd_strerror(int status);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *fdtd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDTD_H */

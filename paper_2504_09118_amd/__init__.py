@@ -1,0 +1,16 @@
+"""MI355X (gfx950) Yee FDTD leapfrog for PEC box cavities.
+
+The compute lives in libfdtd.so (hand-written HIP kernels behind the C ABI of
+include/fdtd.h); this package only binds it. See ``fdtd.Solver``.
+"""
+
+from .fdtd import (  # noqa: F401
+    DIAG_NAMES,
+    FIELD_NAMES,
+    KERNELS,
+    FdtdError,
+    Solver,
+    field_shapes,
+    load_library,
+    required_bytes,
+)

@@ -1,0 +1,730 @@
+// C ABI of libfdtd (declared and documented in include/fdtd.h).
+//
+// Device memory of one solver, carved from one arena (caller-provided or
+// hipMalloc'd), each region 256-byte aligned:
+//   A[6]  state buffer 0 (Ex Ey Ez Hx Hy Hz boxes)
+//   B[6]  state buffer 1 (the fused schedules write the next state here)
+//   Ce[3] per-node E coefficients (only with per-cell eps)
+//   Ch[3] per-node H coefficients (only with per-cell mu)
+//   staging: one dense staggered array in FP64 (host transfers, materials)
+//   diag: FP64 partial sums of the diagnostics
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+
+#include "fdtd.h"
+#include "fdtd_internal.h"
+
+using fdtd::Coefs;
+using fdtd::Fields;
+using fdtd::Geom;
+
+namespace {
+
+constexpr uint32_t kMagic = 0xFD7D2025u;
+constexpr uint32_t kDead = 0xDEADFD7Du;
+
+thread_local std::string g_last_error;
+
+// Live handles: a destroyed or foreign pointer is rejected without being dereferenced.
+std::mutex g_live_mu;
+std::unordered_set<const void *> g_live;
+
+bool is_live(const void *h)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return h && g_live.count(h) != 0;
+}
+
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+    Geom g;
+    size_t esz;
+    size_t box_bytes;
+    size_t off_fields[2][6];
+    size_t off_ce[3], off_ch[3];
+    size_t off_staging, staging_bytes;
+    size_t off_diag;
+    size_t total;
+};
+
+Plan make_plan(int nx, int ny, int nz, int storage, bool ce_arr, bool ch_arr)
+{
+    Plan p{};
+    Geom &g = p.g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.px = (int)round_up((size_t)nx + 1, 64);
+    g.py = ny + 1;
+    g.pz = nz + 1;
+    g.plane = (long long)g.px * g.py;
+    g.box = (long long)round_up((size_t)g.plane * g.pz + 2 * fdtd::kGuardElems, 64);
+    p.esz = storage == FDTD_F64 ? 8 : 4;
+    p.box_bytes = round_up((size_t)g.box * p.esz, 256);
+    size_t off = 0;
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < 6; ++f) {
+            p.off_fields[b][f] = off;
+            off += p.box_bytes;
+        }
+    for (int f = 0; f < 3; ++f) {
+        p.off_ce[f] = ce_arr ? off : SIZE_MAX;
+        if (ce_arr) off += p.box_bytes;
+    }
+    for (int f = 0; f < 3; ++f) {
+        p.off_ch[f] = ch_arr ? off : SIZE_MAX;
+        if (ch_arr) off += p.box_bytes;
+    }
+    p.staging_bytes = round_up((size_t)(nx + 1) * (ny + 1) * (nz + 1) * sizeof(double), 256);
+    p.off_staging = off;
+    off += p.staging_bytes;
+    p.off_diag = off;
+    off += round_up((fdtd::diag_partial_doubles() + 16) * sizeof(double), 256);
+    p.total = off;
+    return p;
+}
+
+}  // namespace
+
+struct fdtd_solver {
+    uint32_t magic;
+    int nx, ny, nz;
+    double dx, dt;
+    int storage, kernel, tb, device, zchunk;
+    hipStream_t stream;
+    bool own_stream;
+    char *arena;
+    size_t arena_bytes;
+    bool own_arena;
+    Plan plan;
+    void *fld[2][6];
+    void *ce[3], *ch[3];
+    bool ce_arr, ch_arr;
+    double ce_s, ch_s;
+    void *staging;
+    double *diag;
+    int cur;
+    long long steps, sweeps;
+    bool failed, fields_set;
+};
+
+namespace {
+
+int check(fdtd_t h)
+{
+    if (!is_live(h) || h->magic != kMagic)
+        return fail(FDTD_E_STATE, "invalid or destroyed solver handle");
+    if (h->failed)
+        return fail(FDTD_E_STATE, "solver is in an error state after a device failure");
+    return FDTD_OK;
+}
+
+int device_fail(fdtd_t h, hipError_t e, const char *what)
+{
+    if (h)
+        h->failed = true;
+    return fail(FDTD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Make the solver's device current for this thread.
+int use_device(fdtd_t h)
+{
+    hipError_t e = hipSetDevice(h->device);
+    if (e != hipSuccess)
+        return device_fail(h, e, "hipSetDevice");
+    return FDTD_OK;
+}
+
+template <typename T>
+Fields<T> fields_of(fdtd_t h, int b)
+{
+    Fields<T> f;
+    for (int q = 0; q < 6; ++q) f.f[q] = (T *)h->fld[b][q];
+    return f;
+}
+
+template <typename T>
+Coefs<T> coefs_of(fdtd_t h)
+{
+    Coefs<T> c;
+    for (int q = 0; q < 3; ++q) {
+        c.ce[q] = (const T *)h->ce[q];
+        c.ch[q] = (const T *)h->ch[q];
+    }
+    c.ce_s = (T)h->ce_s;
+    c.ch_s = (T)h->ch_s;
+    return c;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int scan_material(const double *m, size_t n, double *mn, const char *name)
+{
+    *mn = 1.0;
+    if (!m)
+        return FDTD_OK;
+    double lo = INFINITY;
+    for (size_t q = 0; q < n; ++q) {
+        if (!finite_pos(m[q]))
+            return fail(FDTD_E_ARG, "%s[%zu] = %g is not finite and > 0", name, q, m[q]);
+        lo = m[q] < lo ? m[q] : lo;
+    }
+    *mn = lo;
+    return FDTD_OK;
+}
+
+int resolve_kernel(int kernel, int storage)
+{
+    (void)storage;
+    if (kernel == FDTD_KERNEL_AUTO)
+        return FDTD_KERNEL_FUSED;
+    return kernel;
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    if (!v || !*v)
+        return dflt;
+    return atoi(v);
+}
+
+template <typename T>
+int step_impl(fdtd_t h, long long n)
+{
+    const Coefs<T> c = coefs_of<T>(h);
+    for (long long s = 0; s < n; ++s) {
+        hipError_t e;
+        if (h->kernel == FDTD_KERNEL_PLAIN) {
+            e = fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
+        } else {
+            e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
+                                           h->zchunk, h->stream);
+            h->cur = 1 - h->cur;
+        }
+        if (e != hipSuccess)
+            return device_fail(h, e, "kernel launch");
+        h->steps += 1;
+        h->sweeps += 1;
+    }
+    return FDTD_OK;
+}
+
+template <typename S, typename T>
+hipError_t pack_all(fdtd_t h, const void *const src[6], bool staged)
+{
+    for (int f = 0; f < 6; ++f) {
+        const S *p = (const S *)src[f];
+        if (staged) {
+            int X, Y, Z;
+            fdtd::extents(h->plan.g, f, X, Y, Z);
+            size_t bytes = (size_t)X * Y * Z * sizeof(S);
+            hipError_t e = hipMemcpyAsync(h->staging, src[f], bytes, hipMemcpyHostToDevice, h->stream);
+            if (e != hipSuccess)
+                return e;
+            p = (const S *)h->staging;
+        }
+        hipError_t e = fdtd::launch_pack<S, T>(h->plan.g, f, p, (T *)h->fld[0][f], (T *)h->fld[1][f], h->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, typename S>
+hipError_t unpack_all(fdtd_t h, void *const dst[6], bool staged, void *const *boxes)
+{
+    for (int f = 0; f < 6; ++f) {
+        int X, Y, Z;
+        fdtd::extents(h->plan.g, f, X, Y, Z);
+        size_t bytes = (size_t)X * Y * Z * sizeof(S);
+        S *out = staged ? (S *)h->staging : (S *)dst[f];
+        if (!boxes[f]) {
+            hipError_t e = hipMemsetAsync(out, 0, bytes, h->stream);
+            if (e != hipSuccess)
+                return e;
+        } else {
+            hipError_t e = fdtd::launch_unpack<T, S>(h->plan.g, f, (const T *)boxes[f], out, h->stream);
+            if (e != hipSuccess)
+                return e;
+        }
+        if (staged) {
+            hipError_t e = hipMemcpyAsync(dst[f], h->staging, bytes, hipMemcpyDeviceToHost, h->stream);
+            if (e != hipSuccess)
+                return e;
+            e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess)
+                return e;
+        }
+    }
+    return hipSuccess;
+}
+
+int set_fields_common(fdtd_t h, const void *const src[6], int dtype, bool staged)
+{
+    int st = check(h);
+    if (st)
+        return st;
+    if (!src)
+        return fail(FDTD_E_ARG, "NULL field array");
+    for (int f = 0; f < 6; ++f)
+        if (!src[f])
+            return fail(FDTD_E_ARG, "NULL pointer for field %d", f);
+    if (dtype != FDTD_F32 && dtype != FDTD_F64)
+        return fail(FDTD_E_ARG, "unsupported buffer dtype %d", dtype);
+    if ((st = use_device(h)))
+        return st;
+    hipError_t e;
+    const bool f32 = h->storage == FDTD_F32;
+    if (dtype == FDTD_F32)
+        e = f32 ? pack_all<float, float>(h, src, staged) : pack_all<float, double>(h, src, staged);
+    else
+        e = f32 ? pack_all<double, float>(h, src, staged) : pack_all<double, double>(h, src, staged);
+    if (e == hipSuccess && staged)
+        e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return device_fail(h, e, "set_fields");
+    h->cur = 0;
+    h->steps = 0;
+    h->fields_set = true;
+    return FDTD_OK;
+}
+
+int get_common(fdtd_t h, void *const dst[6], int dtype, bool staged, void *const *boxes)
+{
+    int st = check(h);
+    if (st)
+        return st;
+    if (!dst)
+        return fail(FDTD_E_ARG, "NULL field array");
+    for (int f = 0; f < 6; ++f)
+        if (!dst[f])
+            return fail(FDTD_E_ARG, "NULL pointer for field %d", f);
+    if (dtype != FDTD_F32 && dtype != FDTD_F64)
+        return fail(FDTD_E_ARG, "unsupported buffer dtype %d", dtype);
+    if ((st = use_device(h)))
+        return st;
+    hipError_t e;
+    const bool f32 = h->storage == FDTD_F32;
+    if (dtype == FDTD_F32)
+        e = f32 ? unpack_all<float, float>(h, dst, staged, boxes) : unpack_all<double, float>(h, dst, staged, boxes);
+    else
+        e = f32 ? unpack_all<float, double>(h, dst, staged, boxes)
+                : unpack_all<double, double>(h, dst, staged, boxes);
+    if (e != hipSuccess)
+        return device_fail(h, e, "get_fields");
+    return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_opts_default(fdtd_opts *o)
+{
+    if (!o)
+        return fail(FDTD_E_ARG, "NULL opts");
+    memset(o, 0, sizeof *o);
+    o->storage = FDTD_F32;
+    o->kernel = FDTD_KERNEL_AUTO;
+    return FDTD_OK;
+}
+
+int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdtd_opts *opts, size_t *out)
+{
+    if (!out)
+        return fail(FDTD_E_ARG, "NULL out");
+    if (nx < 2 || ny < 2 || nz < 2)
+        return fail(FDTD_E_ARG, "dims must be >= 2 (got %d %d %d)", nx, ny, nz);
+    fdtd_opts d;
+    fdtd_opts_default(&d);
+    const fdtd_opts *o = opts ? opts : &d;
+    if (o->storage != FDTD_F32 && o->storage != FDTD_F64)
+        return fail(FDTD_E_UNSUPPORTED, "storage dtype %d not built", o->storage);
+    Plan p = make_plan(nx, ny, nz, o->storage, coef && coef->eps_r, coef && coef->mu_r);
+    *out = p.total + 256;  // room to align an arbitrary arena base
+    return FDTD_OK;
+}
+
+int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *coef, const fdtd_opts *opts,
+                fdtd_t *out)
+{
+    if (!out)
+        return fail(FDTD_E_ARG, "NULL out");
+    if (nx < 2 || ny < 2 || nz < 2)
+        return fail(FDTD_E_ARG, "dims must be >= 2 (got %d %d %d)", nx, ny, nz);
+    if ((long long)nx * ny * nz > (1LL << 33))
+        return fail(FDTD_E_ARG, "grid too large");
+    if (!finite_pos(dx) || !finite_pos(dt))
+        return fail(FDTD_E_ARG, "dx and dt must be finite and > 0 (got %g, %g)", dx, dt);
+    fdtd_opts d;
+    fdtd_opts_default(&d);
+    const fdtd_opts *o = opts ? opts : &d;
+    if (o->storage != FDTD_F32 && o->storage != FDTD_F64)
+        return fail(FDTD_E_UNSUPPORTED, "storage dtype %d not built", o->storage);
+    if (o->kernel < FDTD_KERNEL_AUTO || o->kernel > FDTD_KERNEL_TEMPORAL)
+        return fail(FDTD_E_ARG, "unknown kernel %d", o->kernel);
+    int kern = resolve_kernel(o->kernel, o->storage);
+    if (kern == FDTD_KERNEL_SLAB || kern == FDTD_KERNEL_TEMPORAL)
+        return fail(FDTD_E_UNSUPPORTED, "kernel %d not built yet", kern);
+    if (o->arena && o->arena_bytes == 0)
+        return fail(FDTD_E_ARG, "arena given with arena_bytes = 0");
+    const double *eps = coef ? coef->eps_r : nullptr;
+    const double *mu = coef ? coef->mu_r : nullptr;
+    const size_t ncell = (size_t)nx * ny * nz;
+    double eps_min, mu_min;
+    int st;
+    if ((st = scan_material(eps, ncell, &eps_min, "eps_r")))
+        return st;
+    if ((st = scan_material(mu, ncell, &mu_min, "mu_r")))
+        return st;
+    // Courant limit of the cubic Yee grid: c_max dt sqrt(3) / dx < 1, c_max = 1/sqrt(min eps min mu)
+    const double courant = dt * std::sqrt(3.0) / dx;
+    if (!(courant < std::sqrt(eps_min * mu_min)))
+        return fail(FDTD_E_CFL, "dt*sqrt(3)/dx = %.17g violates the Courant limit %.17g", courant,
+                    std::sqrt(eps_min * mu_min));
+
+    Plan p = make_plan(nx, ny, nz, o->storage, eps != nullptr, mu != nullptr);
+    hipError_t e = hipSetDevice(o->device);
+    if (e != hipSuccess)
+        return fail(FDTD_E_DEVICE, "hipSetDevice(%d): %s", o->device, hipGetErrorString(e));
+
+    fdtd_solver *h = new fdtd_solver();
+    h->magic = kMagic;
+    h->nx = nx;
+    h->ny = ny;
+    h->nz = nz;
+    h->dx = dx;
+    h->dt = dt;
+    h->storage = o->storage;
+    h->kernel = kern;
+    h->tb = o->tb_steps > 0 ? o->tb_steps : 1;
+    h->device = o->device;
+    h->zchunk = env_int("FDTD_ZCHUNKS", 0);
+    h->plan = p;
+    h->ce_arr = eps != nullptr;
+    h->ch_arr = mu != nullptr;
+    h->ce_s = dt / dx;
+    h->ch_s = dt / dx;
+    if (h->zchunk <= 0) {
+        // enough workgroups to fill 256 CUs a few times over
+        long long tiles = (long long)((nx + 63) / 64) * ((ny + 7) / 8);
+        int zc = 1;
+        while (tiles * zc < 2048 && nz / (zc * 2) >= 16) zc *= 2;
+        h->zchunk = zc;
+    }
+
+    if (o->stream) {
+        h->stream = (hipStream_t)o->stream;
+        h->own_stream = false;
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(FDTD_E_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        h->own_stream = true;
+    }
+    char *base;
+    if (o->arena) {
+        if (o->arena_bytes < p.total + 256) {
+            if (h->own_stream) (void)hipStreamDestroy(h->stream);
+            delete h;
+            return fail(FDTD_E_NOMEM, "arena of %zu bytes < required %zu", o->arena_bytes, p.total + 256);
+        }
+        h->arena = (char *)o->arena;
+        h->arena_bytes = o->arena_bytes;
+        h->own_arena = false;
+    } else {
+        const char *budget = getenv("FDTD_HBM_BUDGET");
+        if (budget && *budget && (double)(p.total + 256) > atof(budget)) {
+            if (h->own_stream) (void)hipStreamDestroy(h->stream);
+            delete h;
+            return fail(FDTD_E_NOMEM, "required %zu bytes exceed FDTD_HBM_BUDGET=%s", p.total + 256, budget);
+        }
+        void *mem = nullptr;
+        e = hipMalloc(&mem, p.total + 256);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (h->own_stream) (void)hipStreamDestroy(h->stream);
+            delete h;
+            return fail(FDTD_E_NOMEM, "hipMalloc(%zu): %s", p.total + 256, hipGetErrorString(e));
+        }
+        h->arena = (char *)mem;
+        h->arena_bytes = p.total + 256;
+        h->own_arena = true;
+    }
+    base = (char *)round_up((uintptr_t)h->arena, 256);
+    const size_t guard = (size_t)fdtd::kGuardElems * p.esz;
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < 6; ++f) h->fld[b][f] = base + p.off_fields[b][f] + guard;
+    for (int f = 0; f < 3; ++f) {
+        h->ce[f] = h->ce_arr ? base + p.off_ce[f] + guard : nullptr;
+        h->ch[f] = h->ch_arr ? base + p.off_ch[f] + guard : nullptr;
+    }
+    h->staging = base + p.off_staging;
+    h->diag = (double *)(base + p.off_diag);
+
+    e = hipMemsetAsync(base, 0, p.total, h->stream);
+    // materials -> staging -> FP64 coefficient kernel, one material at a time
+    for (int which = 0; which < 2 && e == hipSuccess; ++which) {
+        const double *m = which == 0 ? eps : mu;
+        if (!m)
+            continue;
+        e = hipMemcpyAsync(h->staging, m, ncell * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess)
+            break;
+        if (h->storage == FDTD_F32) {
+            float *ce[3] = {nullptr, nullptr, nullptr}, *ch[3] = {nullptr, nullptr, nullptr};
+            for (int f = 0; f < 3; ++f) (which == 0 ? ce : ch)[f] = (float *)(which == 0 ? h->ce[f] : h->ch[f]);
+            e = fdtd::launch_coef<float>(p.g, dx, dt, which == 0 ? (const double *)h->staging : nullptr,
+                                         which == 1 ? (const double *)h->staging : nullptr, ce, ch, h->stream);
+        } else {
+            double *ce[3] = {nullptr, nullptr, nullptr}, *ch[3] = {nullptr, nullptr, nullptr};
+            for (int f = 0; f < 3; ++f) (which == 0 ? ce : ch)[f] = (double *)(which == 0 ? h->ce[f] : h->ch[f]);
+            e = fdtd::launch_coef<double>(p.g, dx, dt, which == 0 ? (const double *)h->staging : nullptr,
+                                          which == 1 ? (const double *)h->staging : nullptr, ce, ch, h->stream);
+        }
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(h->stream);  // staging is reused by the next material
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        int r = fail(FDTD_E_DEVICE, "create: %s", hipGetErrorString(e));
+        if (h->own_arena) (void)hipFree(h->arena);
+        if (h->own_stream) (void)hipStreamDestroy(h->stream);
+        delete h;
+        return r;
+    }
+    h->fields_set = false;
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live.insert(h);
+    }
+    *out = h;
+    return FDTD_OK;
+}
+
+int fdtd_set_fields(fdtd_t h, const void *const host[6], int host_dtype)
+{
+    return set_fields_common(h, host, host_dtype, true);
+}
+
+int fdtd_set_fields_device(fdtd_t h, const void *const dev[6], int dev_dtype)
+{
+    return set_fields_common(h, dev, dev_dtype, false);
+}
+
+int fdtd_step(fdtd_t h, long long n)
+{
+    int st = check(h);
+    if (st)
+        return st;
+    if (n < 0)
+        return fail(FDTD_E_ARG, "negative step count %lld", n);
+    if (!h->fields_set)
+        return fail(FDTD_E_STATE, "fields were never set");
+    if ((st = use_device(h)))
+        return st;
+    return h->storage == FDTD_F32 ? step_impl<float>(h, n) : step_impl<double>(h, n);
+}
+
+int fdtd_get_fields(fdtd_t h, void *const host[6], int host_dtype)
+{
+    if (int st = check(h))
+        return st;
+    void *const *boxes = h->fld[h->cur];
+    return get_common(h, host, host_dtype, true, boxes);
+}
+
+int fdtd_get_fields_device(fdtd_t h, void *const dev[6], int dev_dtype)
+{
+    if (int st = check(h))
+        return st;
+    void *const *boxes = h->fld[h->cur];
+    return get_common(h, dev, dev_dtype, false, boxes);
+}
+
+int fdtd_get_coefs(fdtd_t h, void *const host[6], int host_dtype)
+{
+    if (int st = check(h))
+        return st;
+    if (!h->ce_arr || !h->ch_arr) {
+        // scalar coefficients: materialise the per-node view the kernels apply
+        // (scalar on updated nodes, 0 on nodes that never change) on the host
+        if (!host)
+            return fail(FDTD_E_ARG, "NULL field array");
+        if (host_dtype != FDTD_F32 && host_dtype != FDTD_F64)
+            return fail(FDTD_E_ARG, "unsupported buffer dtype %d", host_dtype);
+    }
+    void *boxes[6];
+    for (int f = 0; f < 3; ++f) {
+        boxes[f] = h->ce[f];
+        boxes[f + 3] = h->ch[f];
+    }
+    int st = get_common(h, host, host_dtype, true, boxes);
+    if (st)
+        return st;
+    const int nx = h->nx, ny = h->ny, nz = h->nz;
+    for (int f = 0; f < 6; ++f) {
+        const bool scalar = f < 3 ? !h->ce_arr : !h->ch_arr;
+        if (!scalar)
+            continue;
+        int X, Y, Z;
+        fdtd::extents(h->plan.g, f, X, Y, Z);
+        const double sv = h->storage == FDTD_F32 ? (double)(float)(f < 3 ? h->ce_s : h->ch_s)
+                                                 : (f < 3 ? h->ce_s : h->ch_s);
+        for (int k = 0; k < Z; ++k)
+            for (int j = 0; j < Y; ++j)
+                for (int i = 0; i < X; ++i) {
+                    bool fixed;
+                    switch (f) {
+                    case 0: fixed = j == 0 || j == ny || k == 0 || k == nz; break;
+                    case 1: fixed = i == 0 || i == nx || k == 0 || k == nz; break;
+                    case 2: fixed = i == 0 || i == nx || j == 0 || j == ny; break;
+                    case 3: fixed = i == 0 || i == nx; break;
+                    case 4: fixed = j == 0 || j == ny; break;
+                    default: fixed = k == 0 || k == nz; break;
+                    }
+                    const size_t l = (size_t)i + (size_t)X * ((size_t)j + (size_t)Y * k);
+                    const double v = fixed ? 0.0 : sv;
+                    if (host_dtype == FDTD_F64)
+                        ((double *)host[f])[l] = v;
+                    else
+                        ((float *)host[f])[l] = (float)v;
+                }
+    }
+    return FDTD_OK;
+}
+
+int fdtd_sync(fdtd_t h)
+{
+    if (int st = check(h))
+        return st;
+    if (int st = use_device(h))
+        return st;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return device_fail(h, e, "sync");
+    return FDTD_OK;
+}
+
+long long fdtd_steps_done(fdtd_t h)
+{
+    if (!is_live(h) || h->magic != kMagic)
+        return -1;
+    return h->steps;
+}
+
+int fdtd_diag(fdtd_t h, double out[FDTD_DIAG_N])
+{
+    if (int st = check(h))
+        return st;
+    if (!out)
+        return fail(FDTD_E_ARG, "NULL out");
+    if (int st = use_device(h))
+        return st;
+    double *partial = h->diag;
+    double *dev_out = h->diag + fdtd::diag_partial_doubles();
+    hipError_t e;
+    if (h->storage == FDTD_F32)
+        e = fdtd::launch_diag<float>(h->plan.g, fields_of<float>(h, h->cur), coefs_of<float>(h), partial, dev_out,
+                                     h->stream);
+    else
+        e = fdtd::launch_diag<double>(h->plan.g, fields_of<double>(h, h->cur), coefs_of<double>(h), partial,
+                                      dev_out, h->stream);
+    double tmp[8] = {0};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(tmp, dev_out, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return device_fail(h, e, "diag");
+    for (int q = 0; q < FDTD_DIAG_N; ++q) out[q] = tmp[q];
+    return FDTD_OK;
+}
+
+int fdtd_query(fdtd_t h, long long out[8])
+{
+    if (!is_live(h) || h->magic != kMagic)
+        return fail(FDTD_E_STATE, "invalid or destroyed solver handle");
+    if (!out)
+        return fail(FDTD_E_ARG, "NULL out");
+    out[0] = h->kernel;
+    out[1] = h->kernel == FDTD_KERNEL_TEMPORAL ? h->tb : 1;
+    out[2] = h->storage;
+    out[3] = h->sweeps;
+    out[4] = h->ce_arr;
+    out[5] = h->ch_arr;
+    out[6] = h->plan.g.px;
+    out[7] = (long long)h->arena_bytes;
+    return FDTD_OK;
+}
+
+void *fdtd_stream(fdtd_t h)
+{
+    if (!is_live(h) || h->magic != kMagic)
+        return nullptr;
+    return (void *)h->stream;
+}
+
+int fdtd_destroy(fdtd_t h)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        if (!h || g_live.erase(h) == 0)
+            return fail(FDTD_E_STATE, "invalid or destroyed solver handle");
+    }
+    (void)hipSetDevice(h->device);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (h->own_arena)
+        (void)hipFree(h->arena);
+    if (h->own_stream)
+        (void)hipStreamDestroy(h->stream);
+    h->magic = kDead;
+    delete h;
+    if (e != hipSuccess)
+        return fail(FDTD_E_DEVICE, "destroy: pending work failed: %s", hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+const char *fdtd_strerror(int status)
+{
+    switch (status) {
+    case FDTD_OK: return "ok";
+    case FDTD_E_ARG: return "invalid argument";
+    case FDTD_E_CFL: return "time step violates the Courant limit";
+    case FDTD_E_NOMEM: return "not enough device memory";
+    case FDTD_E_DEVICE: return "device error";
+    case FDTD_E_STATE: return "invalid solver state";
+    case FDTD_E_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+    }
+}
+
+const char *fdtd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

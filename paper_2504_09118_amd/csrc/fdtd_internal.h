@@ -1,0 +1,103 @@
+// Internal types of libfdtd: device layout, kernel argument packs, launchers.
+//
+// Device layout. Every component (Ex, Ey, Ez, Hx, Hy, Hz, and the per-node
+// coefficients) lives in its own padded box of px * py * pz elements,
+// x-fastest: element (i, j, k) at base[i + px * (j + py * k)], with
+// px >= nx + 1 a multiple of 64 elements (each 64-lane row segment is one
+// aligned 256-byte access), py = ny + 1, pz = nz + 1. Entries outside a
+// component's staggered extent are padding (zero, never written). Each box
+// starts on a 256-byte boundary after a 256-byte guard.
+//
+// Update domain. Every update of the method lies in the nx*ny*nz cell set
+// (i, j, k) in [0,nx) x [0,ny) x [0,nz); per cell:
+//   Hx if i >= 1, Hy if j >= 1, Hz if k >= 1   (wall-normal H never changes)
+//   Ex if j, k >= 1, Ey if i, k >= 1, Ez if i, j >= 1   (PEC walls never change)
+// and every value the updates read at index nx, ny or nz (x, y, z) is a
+// wall-tangential E node, i.e. exactly 0. Kernels therefore index only the
+// cell domain and substitute 0 beyond it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fdtd {
+
+struct Geom {
+    int nx, ny, nz;
+    int px, py, pz;
+    long long plane;  // px * py
+    long long box;    // elements reserved per component box (incl. guards, 64-aligned)
+    __host__ __device__ long long at(int i, int j, int k) const
+    {
+        return (long long)i + (long long)px * ((long long)j + (long long)py * k);
+    }
+};
+
+constexpr int kGuardElems = 64;
+
+template <typename T>
+struct Fields {
+    T *f[6];  // Ex, Ey, Ez, Hx, Hy, Hz: element (0,0,0) of each box
+};
+
+template <typename T>
+struct Coefs {
+    const T *ce[3];  // per-node Ce boxes, or nullptr when scalar
+    const T *ch[3];  // per-node Ch boxes, or nullptr when scalar
+    T ce_s;          // scalar Ce (interior E nodes) when ce[] is null
+    T ch_s;          // scalar Ch (non-wall H nodes) when ch[] is null
+};
+
+// Kernel schedules (values match fdtd_kernel in include/fdtd.h).
+enum Schedule { kAuto = 0, kPlain = 1, kFused = 2, kSlab = 3, kTemporal = 4 };
+
+// ---- launchers (each returns the first HIP error it meets) ----
+
+// Plain two-sweep step, in place on f.
+template <typename T>
+hipError_t launch_plain_step(const Geom &g, const Fields<T> &f, const Coefs<T> &c, hipStream_t s);
+
+// Fused one-sweep step: reads src, writes dst (src is not modified).
+template <typename T>
+hipError_t launch_fused_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
+                             const Coefs<T> &c, int zchunk, hipStream_t s);
+
+// FP64 coefficient precompute. eps / mu: device per-cell arrays (nx*ny*nz,
+// x-fastest) or nullptr for 1. Writes the three boxes of each kind that are
+// non-null; dt_dx = dt / dx.
+template <typename T>
+hipError_t launch_coef(const Geom &g, double dx, double dt, const double *eps, const double *mu,
+                       T *ce[3], T *ch[3], hipStream_t s);
+
+// Dense staggered buffer (type S) -> padded box (type T) for field f; writes
+// both destinations (dst2 may be null). E fields get 0 on wall-tangential nodes.
+template <typename S, typename T>
+hipError_t launch_pack(const Geom &g, int field, const S *src, T *dst, T *dst2, hipStream_t s);
+
+// Padded box (type T) -> dense staggered buffer (type S) for field f.
+template <typename T, typename S>
+hipError_t launch_unpack(const Geom &g, int field, const T *src, S *dst, hipStream_t s);
+
+// Diagnostics (FP64). partial must hold diag_partial_doubles() doubles.
+size_t diag_partial_doubles();
+template <typename T>
+hipError_t launch_diag(const Geom &g, const Fields<T> &f, const Coefs<T> &c, double *partial,
+                       double *out_dev, hipStream_t s);
+
+// Staggered extents (X, Y, Z) of field f in 0..5.
+__host__ __device__ inline void extents(const Geom &g, int f, int &X, int &Y, int &Z)
+{
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    switch (f) {
+    case 0: X = nx; Y = ny + 1; Z = nz + 1; break;
+    case 1: X = nx + 1; Y = ny; Z = nz + 1; break;
+    case 2: X = nx + 1; Y = ny + 1; Z = nz; break;
+    case 3: X = nx + 1; Y = ny; Z = nz; break;
+    case 4: X = nx; Y = ny + 1; Z = nz; break;
+    default: X = nx; Y = ny; Z = nz + 1; break;
+    }
+}
+
+}  // namespace fdtd

@@ -1,0 +1,297 @@
+"""ctypes binding of libfdtd (include/fdtd.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library. PyTorch is used, when the
+caller asks for it, only to supply device memory (an arena tensor) and the
+stream to enqueue on. Loading fails loudly when libfdtd.so is not built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdtd.so")
+
+OK, E_ARG, E_CFL, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+KERNELS = {"auto": 0, "plain": 1, "fused": 2, "slab": 3, "temporal": 4}
+KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
+DIAG_NAMES = ("energy", "sum_e2", "sum_h2", "max_div_b", "max_e_tan", "nonfinite")
+FIELD_NAMES = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class _Coef(ctypes.Structure):
+    _fields_ = [("eps_r", ctypes.c_void_p), ("mu_r", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [
+        ("storage", ctypes.c_int),
+        ("kernel", ctypes.c_int),
+        ("tb_steps", ctypes.c_int),
+        ("device", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("arena", ctypes.c_void_p),
+        ("arena_bytes", ctypes.c_size_t),
+    ]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libfdtd.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libfdtd.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, ll, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_size_t
+    p6 = ctypes.c_void_p * 6
+    lib.fdtd_opts_default.argtypes = [ctypes.POINTER(_Opts)]
+    lib.fdtd_required_bytes.argtypes = [i, i, i, ctypes.POINTER(_Coef), ctypes.POINTER(_Opts), ctypes.POINTER(sz)]
+    lib.fdtd_create.argtypes = [i, i, i, ctypes.c_double, ctypes.c_double, ctypes.POINTER(_Coef),
+                                ctypes.POINTER(_Opts), ctypes.POINTER(vp)]
+    lib.fdtd_set_fields.argtypes = [vp, p6, i]
+    lib.fdtd_set_fields_device.argtypes = [vp, p6, i]
+    lib.fdtd_step.argtypes = [vp, ll]
+    lib.fdtd_get_fields.argtypes = [vp, p6, i]
+    lib.fdtd_get_fields_device.argtypes = [vp, p6, i]
+    lib.fdtd_get_coefs.argtypes = [vp, p6, i]
+    lib.fdtd_sync.argtypes = [vp]
+    lib.fdtd_steps_done.argtypes = [vp]
+    lib.fdtd_steps_done.restype = ll
+    lib.fdtd_diag.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.fdtd_query.argtypes = [vp, ctypes.POINTER(ll)]
+    lib.fdtd_stream.argtypes = [vp]
+    lib.fdtd_stream.restype = vp
+    lib.fdtd_destroy.argtypes = [vp]
+    lib.fdtd_strerror.argtypes = [i]
+    lib.fdtd_strerror.restype = ctypes.c_char_p
+    lib.fdtd_last_error.restype = ctypes.c_char_p
+    for name in ("fdtd_opts_default", "fdtd_required_bytes", "fdtd_create", "fdtd_set_fields",
+                 "fdtd_set_fields_device", "fdtd_step", "fdtd_get_fields", "fdtd_get_fields_device",
+                 "fdtd_get_coefs", "fdtd_sync", "fdtd_diag", "fdtd_query", "fdtd_destroy"):
+        getattr(lib, name).restype = i
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        lib = load_library()
+        raise FdtdError(status, f"{lib.fdtd_strerror(status).decode()}: {lib.fdtd_last_error().decode()}")
+
+
+def field_shapes(nx: int, ny: int, nz: int) -> tuple:
+    """NumPy (Z, Y, X) shapes of Ex, Ey, Ez, Hx, Hy, Hz in the host layout."""
+    return ((nz + 1, ny + 1, nx), (nz + 1, ny, nx + 1), (nz, ny + 1, nx + 1),
+            (nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx))
+
+
+def _dtype_code(dt) -> int:
+    dt = np.dtype(dt)
+    if dt == np.float64:
+        return F64
+    if dt == np.float32:
+        return F32
+    raise ValueError(f"unsupported dtype {dt}")
+
+
+def _material_array(m, nx, ny, nz):
+    if m is None:
+        return None
+    a = np.ascontiguousarray(m, dtype=np.float64)
+    if a.shape != (nz, ny, nx):
+        raise ValueError(f"material array must have shape (nz, ny, nx) = {(nz, ny, nx)}, got {a.shape}")
+    return a
+
+
+def required_bytes(nx, ny, nz, eps_r=None, mu_r=None, storage="f32", kernel="auto"):
+    lib = load_library()
+    coef = _Coef(eps_r=1 if eps_r is not None else None, mu_r=1 if mu_r is not None else None)
+    opts = _Opts()
+    lib.fdtd_opts_default(ctypes.byref(opts))
+    opts.storage = F32 if storage == "f32" else F64
+    opts.kernel = KERNELS[kernel]
+    out = ctypes.c_size_t(0)
+    _check(lib.fdtd_required_bytes(nx, ny, nz, ctypes.byref(coef), ctypes.byref(opts), ctypes.byref(out)))
+    return out.value
+
+
+class Solver:
+    """One PEC-cavity Yee solver living on one GPU.
+
+    storage: "f32" (default) or "f64" (test-only double-precision fields).
+    kernel: "auto", "plain", "fused", "slab" or "temporal"; tb_steps: steps
+    per sweep for "temporal".
+    stream: a hipStream_t handle (int), a torch.cuda.Stream, or "torch" for
+    torch's current stream; None lets the library create its own stream.
+    arena: "torch" to allocate all device state as one torch uint8 tensor
+    (kept alive by the solver), or None for the library's own hipMalloc.
+    """
+
+    def __init__(self, nx, ny, nz, dx=1.0, dt=None, eps_r=None, mu_r=None, storage="f32", kernel="auto",
+                 tb_steps=0, stream=None, arena=None, device=0):
+        self._lib = load_library()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dx = float(dx)
+        self.dt = float(dt if dt is not None else 0.5 / 3 ** 0.5 * dx)
+        self._h = ctypes.c_void_p(None)
+        self._arena_tensor = None
+        eps = _material_array(eps_r, nx, ny, nz)
+        mu = _material_array(mu_r, nx, ny, nz)
+        coef = _Coef(eps_r=eps.ctypes.data if eps is not None else None,
+                     mu_r=mu.ctypes.data if mu is not None else None)
+        opts = _Opts()
+        self._lib.fdtd_opts_default(ctypes.byref(opts))
+        if storage not in ("f32", "f64"):
+            raise ValueError(f"unsupported storage {storage!r}")
+        opts.storage = F32 if storage == "f32" else F64
+        opts.kernel = KERNELS[kernel]
+        opts.tb_steps = int(tb_steps)
+        opts.device = int(device)
+        if stream is not None:
+            opts.stream = _stream_handle(stream, device)
+        if arena == "torch":
+            import torch
+
+            nbytes = ctypes.c_size_t(0)
+            _check(self._lib.fdtd_required_bytes(nx, ny, nz, ctypes.byref(coef), ctypes.byref(opts),
+                                                 ctypes.byref(nbytes)))
+            self._arena_tensor = torch.empty(nbytes.value, dtype=torch.uint8, device=f"cuda:{device}")
+            opts.arena = self._arena_tensor.data_ptr()
+            opts.arena_bytes = nbytes.value
+        elif arena is not None:
+            raise ValueError("arena must be None or 'torch'")
+        _check(self._lib.fdtd_create(self.nx, self.ny, self.nz, self.dx, self.dt, ctypes.byref(coef),
+                                     ctypes.byref(opts), ctypes.byref(self._h)))
+        self.storage = storage
+
+    # ------------------------------------------------------------------ state
+    @property
+    def shapes(self):
+        return field_shapes(self.nx, self.ny, self.nz)
+
+    def set_fields(self, e, h=None):
+        """Set (E^0, H^{-1/2}) from host arrays (float32 or float64, host layout); H defaults to 0."""
+        arrs = list(e) + (list(h) if h is not None else [np.zeros(s, dtype=np.asarray(e[0]).dtype)
+                                                        for s in self.shapes[3:]])
+        dt = np.asarray(arrs[0]).dtype
+        keep = []
+        for a, s in zip(arrs, self.shapes):
+            a = np.ascontiguousarray(a, dtype=dt)
+            if a.shape != s:
+                raise ValueError(f"field shape {a.shape} != expected {s}")
+            keep.append(a)
+        ptrs = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in keep])
+        _check(self._lib.fdtd_set_fields(self._h, ptrs, _dtype_code(dt)))
+
+    def set_fields_device(self, tensors):
+        """Set the state from six contiguous torch CUDA tensors (float32/float64, host layout shapes)."""
+        import torch
+
+        dt = tensors[0].dtype
+        for t, s in zip(tensors, self.shapes):
+            if tuple(t.shape) != s or not t.is_contiguous() or t.dtype != dt:
+                raise ValueError("device tensors must be contiguous, of one dtype, with the field shapes")
+        code = F32 if dt == torch.float32 else F64 if dt == torch.float64 else None
+        if code is None:
+            raise ValueError(f"unsupported dtype {dt}")
+        ptrs = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in tensors])
+        _check(self._lib.fdtd_set_fields_device(self._h, ptrs, code))
+
+    def get_fields(self, dtype=np.float64):
+        """(Ex, Ey, Ez, Hx, Hy, Hz) = (E^n, H^{n-1/2}) as host arrays; waits for the device."""
+        out = [np.empty(s, dtype=dtype) for s in self.shapes]
+        ptrs = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in out])
+        _check(self._lib.fdtd_get_fields(self._h, ptrs, _dtype_code(dtype)))
+        return tuple(out)
+
+    def get_fields_device(self, tensors):
+        """Write the state into six contiguous torch CUDA tensors (enqueued, no wait)."""
+        import torch
+
+        dt = tensors[0].dtype
+        code = F32 if dt == torch.float32 else F64
+        ptrs = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in tensors])
+        _check(self._lib.fdtd_get_fields_device(self._h, ptrs, code))
+
+    def get_coefs(self, dtype=np.float64):
+        """(Ce_x, Ce_y, Ce_z, Ch_x, Ch_y, Ch_z) in the field layout, as stored on the device."""
+        out = [np.empty(s, dtype=dtype) for s in self.shapes]
+        ptrs = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in out])
+        _check(self._lib.fdtd_get_coefs(self._h, ptrs, _dtype_code(dtype)))
+        return tuple(out)
+
+    # ------------------------------------------------------------------- time
+    def step(self, n: int = 1) -> None:
+        """Enqueue n leapfrog steps (asynchronous)."""
+        _check(self._lib.fdtd_step(self._h, int(n)))
+
+    def sync(self) -> None:
+        _check(self._lib.fdtd_sync(self._h))
+
+    @property
+    def steps_done(self) -> int:
+        return int(self._lib.fdtd_steps_done(self._h))
+
+    def diag(self) -> dict:
+        out = (ctypes.c_double * 6)()
+        _check(self._lib.fdtd_diag(self._h, out))
+        return dict(zip(DIAG_NAMES, list(out)))
+
+    def query(self) -> dict:
+        out = (ctypes.c_longlong * 8)()
+        _check(self._lib.fdtd_query(self._h, out))
+        return {"kernel": KERNEL_NAMES.get(out[0], out[0]), "steps_per_sweep": out[1],
+                "storage": "f32" if out[2] == F32 else "f64", "sweeps": out[3], "ce_array": bool(out[4]),
+                "ch_array": bool(out[5]), "pitch_x": out[6], "device_bytes": out[7]}
+
+    @property
+    def stream(self) -> int:
+        return int(self._lib.fdtd_stream(self._h) or 0)
+
+    def close(self) -> None:
+        if self._h:
+            _check(self._lib.fdtd_destroy(self._h))
+            self._h = ctypes.c_void_p(None)
+        self._arena_tensor = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self._h:
+                self._lib.fdtd_destroy(self._h)
+        except Exception:
+            pass
+
+
+def _stream_handle(stream, device) -> int:
+    if isinstance(stream, int):
+        return stream
+    import torch
+
+    if stream == "torch":
+        handle = torch.cuda.current_stream(device).cuda_stream
+        if handle == 0:
+            raise ValueError("torch's current stream is the null stream; pass a torch.cuda.Stream instead")
+        return handle
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    raise ValueError("stream must be an int handle, a torch.cuda.Stream or 'torch'")

@@ -1,0 +1,123 @@
+"""Host-side checks of the C ABI: exports, argument validation (no GPU needed)."""
+
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2504_09118_amd import fdtd as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtd_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("fdtd_create", "fdtd_set_fields", "fdtd_step", "fdtd_get_fields", "fdtd_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _create(nx=8, ny=8, nz=8, dx=1.0, dt=0.25, eps=None, mu=None, kernel=0):
+    lib = F.load_library()
+    coef = F._Coef(eps_r=eps.ctypes.data if eps is not None else None,
+                   mu_r=mu.ctypes.data if mu is not None else None)
+    opts = F._Opts()
+    lib.fdtd_opts_default(ctypes.byref(opts))
+    opts.kernel = kernel
+    h = ctypes.c_void_p(None)
+    st = lib.fdtd_create(nx, ny, nz, dx, dt, ctypes.byref(coef), ctypes.byref(opts), ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("dims", [(1, 8, 8), (8, 0, 8), (8, 8, -3)])
+def test_create_rejects_bad_dims(dims):
+    st, h = _create(*dims)
+    assert st == F.E_ARG and not h.value
+
+
+@pytest.mark.parametrize("dx,dt", [(0.0, 0.1), (1.0, -0.1), (float("nan"), 0.1), (1.0, float("inf"))])
+def test_create_rejects_bad_spacing(dx, dt):
+    st, _ = _create(dx=dx, dt=dt)
+    assert st == F.E_ARG
+
+
+def test_create_rejects_courant_violation():
+    s_max = 1 / math.sqrt(3)
+    st, _ = _create(dt=s_max * 1.0000001)
+    assert st == F.E_CFL
+    assert b"Courant" in F.load_library().fdtd_last_error()
+
+
+def test_courant_limit_uses_slowest_medium():
+    # eps >= 4 everywhere would allow twice the vacuum step, but one vacuum-like cell does not
+    eps = np.full((8, 8, 8), 4.0)
+    st, h = _create(dt=1.5 / math.sqrt(3), eps=eps)
+    assert st != F.E_CFL  # passes validation (then needs a device)
+    if st == F.OK:
+        F.load_library().fdtd_destroy(h)
+    eps[3, 3, 3] = 1.0
+    st, _ = _create(dt=1.5 / math.sqrt(3), eps=eps)
+    assert st == F.E_CFL
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf")])
+def test_create_rejects_bad_material(bad):
+    eps = np.ones((8, 8, 8))
+    eps[2, 5, 1] = bad
+    st, _ = _create(eps=eps)
+    assert st == F.E_ARG
+    mu = np.ones((8, 8, 8))
+    mu[0, 0, 0] = bad
+    st, _ = _create(mu=mu)
+    assert st == F.E_ARG
+
+
+def test_create_rejects_unknown_kernel():
+    st, _ = _create(kernel=42)
+    assert st == F.E_ARG
+
+
+def test_invalid_handles_are_rejected():
+    lib = F.load_library()
+    bogus = ctypes.c_void_p(0x1234)
+    assert lib.fdtd_step(None, 1) == F.E_STATE
+    assert lib.fdtd_step(bogus, 1) == F.E_STATE
+    assert lib.fdtd_sync(None) == F.E_STATE
+    assert lib.fdtd_steps_done(None) == -1
+    assert lib.fdtd_destroy(bogus) == F.E_STATE
+    ptrs = (ctypes.c_void_p * 6)()
+    assert lib.fdtd_get_fields(None, ptrs, F.F32) == F.E_STATE
+
+
+def test_required_bytes():
+    base = F.required_bytes(64, 48, 40)
+    with_eps = F.required_bytes(64, 48, 40, eps_r=True)
+    with_both = F.required_bytes(64, 48, 40, eps_r=True, mu_r=True)
+    f64 = F.required_bytes(64, 48, 40, storage="f64")
+    px = 128  # nx + 1 rounded up to 64 elements
+    box = px * 49 * 41 * 4
+    assert base >= 12 * box and with_eps - base >= 3 * box and with_both - with_eps >= 3 * box
+    assert f64 > base
+    with pytest.raises(F.FdtdError):
+        F.required_bytes(1, 4, 4)
+
+
+def test_strerror():
+    lib = F.load_library()
+    for code in (F.OK, F.E_ARG, F.E_CFL, F.E_NOMEM, F.E_DEVICE, F.E_STATE, F.E_UNSUPPORTED):
+        assert lib.fdtd_strerror(code)
+    assert lib.fdtd_strerror(F.E_CFL) != lib.fdtd_strerror(F.E_ARG)

@@ -1,0 +1,251 @@
+"""GPU path vs the FP64 oracle (parity mode), through the C ABI.
+
+Parity mode: the oracle is fed the coefficients and the initial fields after
+the same round-to-nearest-even conversion to the storage type that the GPU
+applies, each promoted exactly to FP64 (both sides compute the coefficients
+themselves; the oracle never sees a value the GPU produced). The bar for FP32
+storage is 1e-5 relative L2 over all six arrays; FP64 storage 1e-13.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import cavity_inputs as ci
+import oracle
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+
+S = 0.5 / math.sqrt(3.0)
+KERNELS = ["plain", "fused"]
+
+
+def _solver(*a, **kw):
+    from paper_2504_09118_amd import Solver
+
+    return Solver(*a, **kw)
+
+
+def rel_l2(got, ref):
+    num = math.sqrt(sum(float(np.sum((np.asarray(a, np.float64) - b) ** 2)) for a, b in zip(got, ref)))
+    den = math.sqrt(sum(float(np.sum(b ** 2)) for b in ref))
+    return num / den
+
+
+def oracle_reference(nx, ny, nz, e_init, h_init, eps, mu, steps, storage=np.float32, dt=S):
+    """Oracle run in parity mode: coefficients and init rounded to the storage type."""
+    ce = oracle.coef_e(nx, ny, nz, 1.0, dt, eps)
+    ch = oracle.coef_h(nx, ny, nz, 1.0, dt, mu)
+    if storage != np.float64:
+        ce, ch = oracle.round_to(ce, storage), oracle.round_to(ch, storage)
+        e_init = [np.asarray(a).astype(storage).astype(np.float64) for a in e_init]
+        if h_init is not None:
+            h_init = [np.asarray(a).astype(storage).astype(np.float64) for a in h_init]
+    ref = oracle.make_state(e_init, h_init)
+    oracle.run(ref, ce, ch, steps)
+    return ref
+
+
+def run_gpu(nx, ny, nz, e_init, h_init, eps, mu, steps, kernel="auto", storage="f32", dt=S):
+    with _solver(nx, ny, nz, 1.0, dt, eps_r=eps, mu_r=mu, kernel=kernel, storage=storage) as s:
+        s.set_fields(e_init, h_init)
+        s.step(steps)
+        out = s.get_fields()
+        assert s.steps_done == steps
+    return out
+
+
+def test_coefficients_bit_exact():
+    nx, ny, nz = 37, 29, 23
+    eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=6)
+    mu = ci.uniform_cell_eps(nx, ny, nz, seed=8, lo=1.0, hi=2.0)
+    dt = 0.3
+    ce = oracle.coef_e(nx, ny, nz, 1.0, dt, eps)
+    ch = oracle.coef_h(nx, ny, nz, 1.0, dt, mu)
+    for storage, dt_np in (("f32", np.float32), ("f64", np.float64)):
+        with _solver(nx, ny, nz, 1.0, dt, eps_r=eps, mu_r=mu, storage=storage) as s:
+            got = s.get_coefs(np.float64)
+        for g, r in zip(got, ce + ch):
+            assert np.array_equal(g, r.astype(dt_np).astype(np.float64))
+
+
+def test_scalar_coefficients_view():
+    nx, ny, nz = 9, 7, 5
+    with _solver(nx, ny, nz, 1.0, S) as s:
+        got = s.get_coefs(np.float64)
+    ce = oracle.round_to(oracle.coef_e(nx, ny, nz, 1.0, S), np.float32)
+    ch = oracle.round_to(oracle.coef_h(nx, ny, nz, 1.0, S), np.float32)
+    for g, r in zip(got, ce + ch):
+        assert np.array_equal(g, r)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_parity_cavity_32_fp32(kernel):
+    # 32^3 vacuum cavity, random E (seed 1), H = 0, 100 steps
+    n, steps = 32, 100
+    e = ci.random_e(n, n, n, seed=1, dtype=np.float32)
+    got = run_gpu(n, n, n, e, None, None, None, steps, kernel=kernel)
+    ref = oracle_reference(n, n, n, e, None, None, None, steps)
+    err = rel_l2(got, ref)
+    print(f"\n32^3 fp32 {kernel}: rel-L2 = {err:.3e}")
+    assert err < 1e-5
+    assert oracle.tangential_max(got) == 0.0
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_parity_cavity_32_fp64(kernel):
+    n, steps = 32, 100
+    e = ci.random_e(n, n, n, seed=1)
+    got = run_gpu(n, n, n, e, None, None, None, steps, kernel=kernel, storage="f64")
+    ref = oracle_reference(n, n, n, e, None, None, None, steps, storage=np.float64)
+    err = rel_l2(got, ref)
+    print(f"\n32^3 fp64 {kernel}: rel-L2 = {err:.3e}")
+    assert err < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(32, 32, 32), (8, 6, 10)])
+def test_te101_closed_form_gpu(dims):
+    nx, ny, nz = dims
+    steps = 1000
+    e0 = ci.te101_e(nx, ny, nz)
+    c32 = float(np.float32(S))
+    with _solver(nx, ny, nz, 1.0, S) as s:
+        s.set_fields([a.astype(np.float32) for a in e0])
+        s.step(steps)
+        got = s.get_fields()
+    a = pins.te101_amplitude(steps, c32, c32, nx, nz)
+    e0_32 = e0[1].astype(np.float32).astype(np.float64)
+    err = max(np.abs(got[0]).max(), np.abs(got[2]).max(), np.abs(got[1] - a * e0_32).max())
+    print(f"\nTE101 {dims} fp32, {steps} steps: amplitude {a:.6f}, max-abs err {err:.3e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_parity_ragged_medium(kernel):
+    # several x/y tiles with ragged tails, z chunks, per-node Ce and Ch, random H too
+    nx, ny, nz, steps = 70, 19, 37, 300
+    eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=8)
+    mu = ci.uniform_cell_eps(nx, ny, nz, seed=9, lo=1.0, hi=1.5)
+    e = ci.random_e(nx, ny, nz, seed=3, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=4, dtype=np.float32)
+    got = run_gpu(nx, ny, nz, e, h, eps, mu, steps, kernel=kernel)
+    ref = oracle_reference(nx, ny, nz, e, h, eps, mu, steps)
+    err = rel_l2(got, ref)
+    print(f"\n{nx}x{ny}x{nz} medium fp32 {kernel}: rel-L2 = {err:.3e}")
+    assert err < 1e-5
+    assert oracle.tangential_max(got) == 0.0
+
+
+def test_kernels_bitwise_equal(monkeypatch):
+    nx, ny, nz, steps = 70, 19, 37, 40
+    eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=8)
+    e = ci.random_e(nx, ny, nz, seed=5, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=6, dtype=np.float32)
+    outs = {}
+    for kernel, zc in (("plain", None), ("fused", "1"), ("fused", "3"), ("fused", "8")):
+        if zc is None:
+            monkeypatch.delenv("FDTD_ZCHUNKS", raising=False)
+        else:
+            monkeypatch.setenv("FDTD_ZCHUNKS", zc)
+        outs[(kernel, zc)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel)
+    base = outs[("plain", None)]
+    for key, out in outs.items():
+        for a, b in zip(out, base):
+            assert np.array_equal(a, b), key
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_resume_is_bitwise(kernel):
+    nx, ny, nz, n = 40, 24, 20, 37
+    e = ci.random_e(nx, ny, nz, seed=7, dtype=np.float32)
+    with _solver(nx, ny, nz, 1.0, S, kernel=kernel) as s:
+        s.set_fields(e)
+        s.step(2 * n)
+        straight = s.get_fields(np.float32)
+        s.set_fields(e)
+        s.step(n)
+        mid = s.get_fields(np.float32)
+    with _solver(nx, ny, nz, 1.0, S, kernel=kernel) as s:
+        s.set_fields(mid[:3], mid[3:])
+        s.step(n)
+        resumed = s.get_fields(np.float32)
+    for a, b in zip(straight, resumed):
+        assert np.array_equal(a, b)
+
+
+def test_energy_diag_matches_oracle_and_is_conserved():
+    nx, ny, nz = 30, 26, 22
+    eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=5)
+    e = ci.random_e(nx, ny, nz, seed=2, dtype=np.float32)
+    with _solver(nx, ny, nz, 1.0, S, eps_r=eps) as s:
+        s.set_fields(e)
+        d0 = s.diag()
+        state = s.get_fields()
+        ce = oracle.round_to(oracle.coef_e(nx, ny, nz, 1.0, S, eps), np.float32)
+        ch = oracle.round_to(oracle.coef_h(nx, ny, nz, 1.0, S), np.float32)
+        w_ref, se_ref, sh_ref = oracle.energy(state, ce, ch)
+        assert abs(d0["energy"] - w_ref) <= 1e-12 * w_ref
+        assert abs(d0["sum_e2"] - se_ref) <= 1e-12 * se_ref
+        assert d0["max_e_tan"] == 0.0 and d0["nonfinite"] == 0
+        s.step(500)
+        d1 = s.diag()
+        state = s.get_fields()
+        w1 = oracle.energy(state, ce, ch)[0]
+        assert abs(d1["energy"] - w1) <= 1e-10 * w1
+        drift = abs(d1["energy"] - d0["energy"]) / d0["energy"]
+        print(f"\nenergy drift over 500 fp32 steps: {drift:.3e}; max div B {d1['max_div_b']:.3e}")
+        assert drift < 1e-5
+        assert d1["max_e_tan"] == 0.0
+
+
+def _crop(fields, lo, hi):
+    """Sub-cavity of cells [lo, hi) (x, y, z) with each component's staggered extent."""
+    (a0, b0, c0), (a1, b1, c1) = lo, hi
+    assert len(fields) in (3, 6)
+    cell_axes = {0: (0,), 1: (1,), 2: (2,), 3: (1, 2), 4: (0, 2), 5: (0, 1)}  # axes where a field is cell-centred
+    out = []
+    for f, arr in enumerate(fields):
+        sl = []
+        for ax, (l, h) in zip((2, 1, 0), ((c0, c1), (b0, b1), (a0, a1))):
+            cell = ax in cell_axes[f]
+            sl.append(slice(l, h if cell else h + 1))
+        out.append(np.ascontiguousarray(arr[tuple(sl)]))
+    return out
+
+
+def test_full_size_sampled_parity():
+    """512^3 cavity with spherical inclusions, the benchmark's launch configuration:
+    after a few steps, sampled nodes match the oracle run on a crop around each node
+    (the crop margin exceeds the dependency cone of one cell per step)."""
+    n, steps, margin = 512, 6, 9
+    eps = ci.sphere_eps(n, n, n, seed=33)
+    e = ci.random_e(n, n, n, seed=3, dtype=np.float32)
+    with _solver(n, n, n, 1.0, S, eps_r=eps) as s:
+        s.set_fields(e)
+        s.step(steps)
+        d = s.diag()
+        got = s.get_fields(np.float32)
+    assert d["max_e_tan"] == 0.0 and d["nonfinite"] == 0
+    rng = np.random.default_rng(1234)
+    picks = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n // 2, n - 1), (n // 2, 0, 5), (63, 64, 64), (64, 7, 8)]
+    picks += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(10)]
+    worst = 0.0
+    for (i, j, k) in picks:
+        lo = (max(0, i - margin), max(0, j - margin), max(0, k - margin))
+        hi = (min(n, i + margin + 1), min(n, j + margin + 1), min(n, k + margin + 1))
+        cx, cy, cz = hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]
+        sub = _crop(list(e), lo, hi)
+        sub_h = [np.zeros(shp) for name, shp in oracle.shapes(cx, cy, cz).items() if name[0] == "H"]
+        sub_eps = np.ascontiguousarray(eps[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]])
+        ref = oracle_reference(cx, cy, cz, sub, sub_h, sub_eps, None, steps)
+        gsub = _crop(got, lo, hi)
+        li, lj, lk = i - lo[0], j - lo[1], k - lo[2]
+        for f in range(6):
+            r = ref[f][lk, lj, li]
+            g = gsub[f][lk, lj, li]
+            worst = max(worst, abs(g - r) / max(abs(r), 1.0))
+    print(f"\n512^3 sampled parity after {steps} steps: worst |diff| = {worst:.3e}")
+    assert worst < 1e-5
