@@ -138,10 +138,34 @@ def main() -> int:
         "energy_check": {"nonfinite": d["nonfinite"], "max_e_tan": d["max_e_tan"]},
     }
 
+    result["copy_probe"] = copy_probe(stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(e, eps, nx, ny, nz, dx, dt, args.cpu_steps)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def copy_probe(stream, nbytes: int = 2 << 30, reps: int = 10):
+    """Achievable HBM bandwidth: the library's 16-byte streaming copy of 2 GiB (read + write counted)."""
+    import torch
+
+    from paper_2504_09118_amd.fdtd import probe_copy
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    h = stream.cuda_stream
+    for _ in range(2):
+        probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, h)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, h)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    return {"GBs": round(2 * nbytes / (ms / 1e3) / 1e9, 1), "bytes_read_per_launch": nbytes,
+            "bytes_written_per_launch": nbytes, "avg_launch_ms": round(ms, 4)}
 
 
 def cpu_baseline(e32, eps, nx, ny, nz, dx, dt, steps):

@@ -189,6 +189,16 @@ void *fdtd_stream(fdtd_t h);
 /* Release device memory the library allocated (not a caller arena) and the handle. */
 int fdtd_destroy(fdtd_t h);
 
+/*
+ * Measurement helper (not part of the method): enqueue a plain 16-byte-wide
+ * streaming copy of `bytes` bytes from src to dst (device pointers, 16-byte
+ * aligned, bytes a multiple of 16) on `stream` (hipStream_t or NULL). It
+ * reads and writes a known number of bytes, which gives the achievable HBM
+ * bandwidth and calibrates hardware memory counters. FDTD_E_ARG on a bad
+ * pointer or size, FDTD_E_DEVICE if the launch fails.
+ */
+int fdtd_probe_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 /* Static text for a status code. */
 const char *fdtd_strerror(int status);
 

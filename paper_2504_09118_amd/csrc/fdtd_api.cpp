@@ -112,7 +112,7 @@ struct fdtd_solver {
     uint32_t magic;
     int nx, ny, nz;
     double dx, dt;
-    int storage, kernel, tb, device, zchunk;
+    int storage, kernel, tb, device, zchunk, variant;
     hipStream_t stream;
     bool own_stream;
     char *arena;
@@ -199,7 +199,7 @@ int resolve_kernel(int kernel, int storage)
 {
     (void)storage;
     if (kernel == FDTD_KERNEL_AUTO)
-        return FDTD_KERNEL_FUSED;
+        return FDTD_KERNEL_SLAB;
     return kernel;
 }
 
@@ -219,6 +219,10 @@ int step_impl(fdtd_t h, long long n)
         hipError_t e;
         if (h->kernel == FDTD_KERNEL_PLAIN) {
             e = fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
+        } else if (h->kernel == FDTD_KERNEL_SLAB) {
+            e = fdtd::launch_slab_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
+                                          h->zchunk, h->variant, h->stream);
+            h->cur = 1 - h->cur;
         } else {
             e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
                                            h->zchunk, h->stream);
@@ -387,7 +391,7 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     if (o->kernel < FDTD_KERNEL_AUTO || o->kernel > FDTD_KERNEL_TEMPORAL)
         return fail(FDTD_E_ARG, "unknown kernel %d", o->kernel);
     int kern = resolve_kernel(o->kernel, o->storage);
-    if (kern == FDTD_KERNEL_SLAB || kern == FDTD_KERNEL_TEMPORAL)
+    if (kern == FDTD_KERNEL_TEMPORAL)
         return fail(FDTD_E_UNSUPPORTED, "kernel %d not built yet", kern);
     if (o->arena && o->arena_bytes == 0)
         return fail(FDTD_E_ARG, "arena given with arena_bytes = 0");
@@ -423,19 +427,29 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     h->tb = o->tb_steps > 0 ? o->tb_steps : 1;
     h->device = o->device;
     h->zchunk = env_int("FDTD_ZCHUNKS", 0);
+    h->variant = env_int("FDTD_SLAB_VARIANT", 0);
     h->plan = p;
     h->ce_arr = eps != nullptr;
     h->ch_arr = mu != nullptr;
     h->ce_s = dt / dx;
     h->ch_s = dt / dx;
     if (h->zchunk <= 0) {
-        // enough workgroups to fill 256 CUs a few times over
-        long long tiles = (long long)((nx + 63) / 64) * ((ny + 7) / 8);
+        // split z so the launch has enough workgroups to cover the 256 CUs several times
+        long long tiles;
+        int target;
+        if (kern == FDTD_KERNEL_SLAB) {
+            const int v = h->storage == FDTD_F64 ? 3 : h->variant;
+            const int own = fdtd::slab_rows(v) - 2, w = fdtd::slab_width(v);
+            tiles = (long long)((nx + w - 1) / w) * ((ny + own - 1) / own);
+            target = fdtd::slab_rows(v) == 16 ? 1024 : 2048;
+        } else {
+            tiles = (long long)((nx + 63) / 64) * ((ny + 7) / 8);
+            target = 2048;
+        }
         int zc = 1;
-        while (tiles * zc < 2048 && nz / (zc * 2) >= 16) zc *= 2;
+        while (tiles * zc < target && nz / (zc * 2) >= 16) zc *= 2;
         h->zchunk = zc;
     }
-
     if (o->stream) {
         h->stream = (hipStream_t)o->stream;
         h->own_stream = false;

@@ -64,6 +64,16 @@ template <typename T>
 hipError_t launch_fused_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                              const Coefs<T> &c, int zchunk, hipStream_t s);
 
+// Slab step (fused sweep with V-wide lanes, prefetch and XCD-aware tiles):
+// reads src, writes dst. variant selects the tile shape (0 = default).
+template <typename T>
+hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
+                            const Coefs<T> &c, int zchunk, int variant, hipStream_t s);
+
+// Tile rows owned per workgroup (rows - 2) and tile width of a slab variant.
+int slab_rows(int variant);
+int slab_width(int variant);
+
 // FP64 coefficient precompute. eps / mu: device per-cell arrays (nx*ny*nz,
 // x-fastest) or nullptr for 1. Writes the three boxes of each kind that are
 // non-null; dt_dx = dt / dx.

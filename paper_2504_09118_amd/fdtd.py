@@ -79,6 +79,8 @@ def load_library():
     lib.fdtd_strerror.argtypes = [i]
     lib.fdtd_strerror.restype = ctypes.c_char_p
     lib.fdtd_last_error.restype = ctypes.c_char_p
+    lib.fdtd_probe_copy.argtypes = [vp, vp, sz, vp]
+    lib.fdtd_probe_copy.restype = i
     for name in ("fdtd_opts_default", "fdtd_required_bytes", "fdtd_create", "fdtd_set_fields",
                  "fdtd_set_fields_device", "fdtd_step", "fdtd_get_fields", "fdtd_get_fields_device",
                  "fdtd_get_coefs", "fdtd_sync", "fdtd_diag", "fdtd_query", "fdtd_destroy"):
@@ -280,6 +282,11 @@ class Solver:
                 self._lib.fdtd_destroy(self._h)
         except Exception:
             pass
+
+
+def probe_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream: int = 0) -> None:
+    """Enqueue the library's streaming copy (bandwidth probe) between two device buffers."""
+    _check(load_library().fdtd_probe_copy(dst_ptr, src_ptr, nbytes, stream or None))
 
 
 def _stream_handle(stream, device) -> int:

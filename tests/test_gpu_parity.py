@@ -20,7 +20,7 @@ from tests import pins
 pytestmark = pytest.mark.gpu
 
 S = 0.5 / math.sqrt(3.0)
-KERNELS = ["plain", "fused"]
+KERNELS = ["plain", "fused", "slab"]
 
 
 def _solver(*a, **kw):
@@ -145,13 +145,16 @@ def test_kernels_bitwise_equal(monkeypatch):
     e = ci.random_e(nx, ny, nz, seed=5, dtype=np.float32)
     h = ci.random_h(nx, ny, nz, seed=6, dtype=np.float32)
     outs = {}
-    for kernel, zc in (("plain", None), ("fused", "1"), ("fused", "3"), ("fused", "8")):
-        if zc is None:
-            monkeypatch.delenv("FDTD_ZCHUNKS", raising=False)
-        else:
-            monkeypatch.setenv("FDTD_ZCHUNKS", zc)
-        outs[(kernel, zc)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel)
-    base = outs[("plain", None)]
+    cases = [("plain", None, None), ("fused", "1", None), ("fused", "3", None), ("fused", "8", None)]
+    cases += [("slab", zc, var) for var in ("0", "1", "2", "3") for zc in ("1", "3", "8")]
+    for kernel, zc, var in cases:
+        for name, val in (("FDTD_ZCHUNKS", zc), ("FDTD_SLAB_VARIANT", var)):
+            if val is None:
+                monkeypatch.delenv(name, raising=False)
+            else:
+                monkeypatch.setenv(name, val)
+        outs[(kernel, zc, var)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel)
+    base = outs[("plain", None, None)]
     for key, out in outs.items():
         for a, b in zip(out, base):
             assert np.array_equal(a, b), key
