@@ -112,7 +112,7 @@ struct fdtd_solver {
     uint32_t magic;
     int nx, ny, nz;
     double dx, dt;
-    int storage, kernel, tb, device, zchunk, variant;
+    int storage, kernel, tb, device, zchunk, tzchunk, variant;
     hipStream_t stream;
     bool own_stream;
     char *arena;
@@ -212,22 +212,45 @@ int env_int(const char *name, int dflt)
 }
 
 template <typename T>
-int step_impl(fdtd_t h, long long n)
+hipError_t launch_one(fdtd_t h, int kernel, int ts)
 {
     const Coefs<T> c = coefs_of<T>(h);
-    for (long long s = 0; s < n; ++s) {
-        hipError_t e;
-        if (h->kernel == FDTD_KERNEL_PLAIN) {
-            e = fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
-        } else if (h->kernel == FDTD_KERNEL_SLAB) {
-            e = fdtd::launch_slab_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                          h->zchunk, h->variant, h->stream);
-            h->cur = 1 - h->cur;
-        } else {
-            e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                           h->zchunk, h->stream);
-            h->cur = 1 - h->cur;
-        }
+    if (kernel == FDTD_KERNEL_PLAIN)
+        return fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
+    hipError_t e;
+    if (kernel == FDTD_KERNEL_SLAB)
+        e = fdtd::launch_slab_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c, h->zchunk,
+                                      h->variant, h->stream);
+    else if (kernel == FDTD_KERNEL_TEMPORAL)
+        e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
+                                          h->tzchunk, ts, h->stream);
+    else
+        e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c, h->zchunk,
+                                       h->stream);
+    h->cur = 1 - h->cur;
+    return e;
+}
+
+template <typename T>
+int step_impl(fdtd_t h, long long n)
+{
+    // temporal: floor(n / tb) sweeps of tb steps, the remainder as single-step slab sweeps
+    // (the same bits either way)
+    long long sweeps_tb = 0, singles = n;
+    if (h->kernel == FDTD_KERNEL_TEMPORAL) {
+        sweeps_tb = n / h->tb;
+        singles = n % h->tb;
+    }
+    for (long long s = 0; s < sweeps_tb; ++s) {
+        hipError_t e = launch_one<T>(h, FDTD_KERNEL_TEMPORAL, h->tb);
+        if (e != hipSuccess)
+            return device_fail(h, e, "kernel launch");
+        h->steps += h->tb;
+        h->sweeps += 1;
+    }
+    const int single_kernel = h->kernel == FDTD_KERNEL_TEMPORAL ? FDTD_KERNEL_SLAB : h->kernel;
+    for (long long s = 0; s < singles; ++s) {
+        hipError_t e = launch_one<T>(h, single_kernel, 1);
         if (e != hipSuccess)
             return device_fail(h, e, "kernel launch");
         h->steps += 1;
@@ -391,8 +414,10 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     if (o->kernel < FDTD_KERNEL_AUTO || o->kernel > FDTD_KERNEL_TEMPORAL)
         return fail(FDTD_E_ARG, "unknown kernel %d", o->kernel);
     int kern = resolve_kernel(o->kernel, o->storage);
-    if (kern == FDTD_KERNEL_TEMPORAL)
-        return fail(FDTD_E_UNSUPPORTED, "kernel %d not built yet", kern);
+    if (kern == FDTD_KERNEL_TEMPORAL && o->storage != FDTD_F32)
+        return fail(FDTD_E_UNSUPPORTED, "the temporal kernel is built for FP32 storage only");
+    if (kern == FDTD_KERNEL_TEMPORAL && (o->tb_steps < 0 || o->tb_steps > 3))
+        return fail(FDTD_E_ARG, "tb_steps must be 1..3 (0: default 2), got %d", o->tb_steps);
     if (o->arena && o->arena_bytes == 0)
         return fail(FDTD_E_ARG, "arena given with arena_bytes = 0");
     const double *eps = coef ? coef->eps_r : nullptr;
@@ -424,7 +449,7 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     h->dt = dt;
     h->storage = o->storage;
     h->kernel = kern;
-    h->tb = o->tb_steps > 0 ? o->tb_steps : 1;
+    h->tb = kern == FDTD_KERNEL_TEMPORAL ? (o->tb_steps > 0 ? o->tb_steps : 2) : 1;
     h->device = o->device;
     h->zchunk = env_int("FDTD_ZCHUNKS", 0);
     h->variant = env_int("FDTD_SLAB_VARIANT", 0);
@@ -449,6 +474,15 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         int zc = 1;
         while (tiles * zc < target && nz / (zc * 2) >= 16) zc *= 2;
         h->zchunk = zc;
+    }
+    h->tzchunk = env_int("FDTD_TZCHUNKS", 0);
+    if (h->tzchunk <= 0) {
+        // temporal sweeps redo 2*tb-1 planes per z-chunk: keep chunks >= 48 planes
+        const int own = fdtd::temporal_own_rows(h->tb);
+        const long long tiles = (long long)((nx + 127) / 128) * ((ny + own - 1) / own);
+        int zc = 1;
+        while (tiles * zc < 1024 && nz / (zc * 2) >= 48) zc *= 2;
+        h->tzchunk = zc;
     }
     if (o->stream) {
         h->stream = (hipStream_t)o->stream;

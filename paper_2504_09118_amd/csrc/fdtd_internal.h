@@ -70,6 +70,13 @@ template <typename T>
 hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                             const Coefs<T> &c, int zchunk, int variant, hipStream_t s);
 
+// Temporal step: ts (1..3) leapfrog steps in one sweep; reads src, writes dst.
+// Built for FP32 storage only.
+template <typename T>
+hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
+                                const Coefs<T> &c, int zchunk, int ts, hipStream_t s);
+int temporal_own_rows(int ts);
+
 // Tile rows owned per workgroup (rows - 2) and tile width of a slab variant.
 int slab_rows(int variant);
 int slab_width(int variant);

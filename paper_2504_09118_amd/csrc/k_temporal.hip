@@ -1,0 +1,451 @@
+// Temporal schedule: TS full leapfrog steps per sweep over HBM.
+//
+// The paper blocks only within one step (Sec. 3: tiling, sibling fusion);
+// here one z-marching sweep advances the state by TS steps, so the six
+// components and the coefficients cross HBM once per TS steps.
+//
+// Structure (per workgroup: an x-y tile of 64V own columns x (R - 2 TS) own
+// rows, marching a z-chunk):
+//   - stage s = 1..TS computes step n+s on plane p_s = k - (s-1) at loop
+//     index k: H^{n+s-1/2}(p_s) from E^{n+s-1} at planes p_s and p_s+1, then
+//     E^{n+s}(p_s) from H^{n+s-1/2} at planes p_s and p_s-1. Stage s-1 has
+//     produced E^{n+s-1}(p_s+1) earlier in the same iteration, so each stage
+//     lags the previous one by exactly one plane;
+//   - every stage works on the tile grown by TS cells on each side in x and
+//     y (the dependency cone of TS steps); the ring of cells that see the
+//     missing neighbours shrinks by one cell per stage, so the own cells of
+//     the last stage are exact. Rows are overlapped: wave r owns row
+//     j0 - TS + r; one extra wave holds the x-halo columns of all rows as
+//     V-wide vectors, so every cell runs the same code;
+//   - E of every stage and H of the current stage are exchanged through LDS
+//     (one E buffer per stage, two alternating H buffers), TS + 1 barriers
+//     per plane;
+//   - stage-1 inputs for plane k+1 are prefetched at the top of plane k;
+//     later stages take their inputs from registers of the previous stage;
+//   - a z-chunk starts TS planes early and ends TS-1 planes late so every
+//     stage sees exact inputs on the planes it stores.
+// Only the last stage stores, only own cells. Arithmetic per node is
+// curl_update with the operand order of every other schedule: TS sweeps of
+// this kernel equal TS single steps bit for bit.
+#include "fdtd_internal.h"
+#include "yee_update.h"
+
+namespace fdtd {
+namespace {
+
+constexpr int kXcds = 8;
+
+#define FDTD_GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ FDTD_GLOBAL char *uni(const void *p)
+{
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (FDTD_GLOBAL char *)(((unsigned long long)hi << 32) | lo);
+}
+
+template <typename T>
+struct V2 {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T>
+__device__ __forceinline__ typename V2<T>::type ld2(const T *plane, unsigned boff)
+{
+    return *(FDTD_GLOBAL const typename V2<T>::type *)(uni(plane) + boff);
+}
+
+template <typename T>
+__device__ __forceinline__ void st2(T *plane, unsigned boff, const typename V2<T>::type &x)
+{
+    *(FDTD_GLOBAL typename V2<T>::type *)(uni(plane) + boff) = x;
+}
+
+template <typename T>
+__device__ __forceinline__ void st1(T *plane, unsigned boff, T x)
+{
+    *(FDTD_GLOBAL T *)(uni(plane) + boff) = x;
+}
+
+template <typename T, int TS, bool CE_ARR, bool CH_ARR>
+__global__ void __launch_bounds__(1024)
+    k_temporal(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles)
+{
+    constexpr int V = 2;                    // cells per lane (x)
+    constexpr int R = 15;                   // row waves; wave R holds the x-halo
+    constexpr int W = 64 * V;               // own columns
+    constexpr int NVH = (TS + V - 1) / V;   // halo vectors per side
+    constexpr int HX = NVH * V;             // halo columns per side
+    constexpr int LP = HX + W + HX + V;     // LDS row pitch (one pad vector at the end)
+    constexpr int RB = R + 2;               // LDS rows (one pad row each side)
+    using vec = typename V2<T>::type;
+    __shared__ __attribute__((aligned(16))) T sE[TS][3][RB][LP];  // E input of each stage, plane p_s
+    __shared__ __attribute__((aligned(16))) T sH[2][3][RB][LP];   // H of the current stage (alternating)
+
+    const int nper = (ntiles + kXcds - 1) / kXcds;
+    const int b = blockIdx.x;
+    const int t = (b % kXcds) * nper + b / kXcds;
+    if (t >= ntiles)
+        return;  // the whole workgroup leaves before any barrier
+    const int tile_x = t % ntx;
+    const int tile_y = (t / ntx) % nty;
+    const int zc = t / (ntx * nty);
+
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const long long P = g.plane;
+    const int px = g.px;
+    const int i0 = tile_x * W;
+    const int j0 = tile_y * (R - 2 * TS);
+    const int kb = zc * kchunk;
+    const int ke = min(nz, kb + kchunk);
+
+    // zero the LDS once: pad rows and columns are read (by halo cells only) but never written
+    {
+        T *flatE = &sE[0][0][0][0];
+        T *flatH = &sH[0][0][0][0];
+        const int tid = threadIdx.y * 64 + threadIdx.x;
+        for (int q = tid; q < TS * 3 * RB * LP; q += 64 * (R + 1)) flatE[q] = 0;
+        for (int q = tid; q < 2 * 3 * RB * LP; q += 64 * (R + 1)) flatH[q] = 0;
+    }
+
+    // lane geometry: (row, first local column c0) of the lane's V cells
+    const int wave = threadIdx.y, lane = threadIdx.x;
+    int row, c0;
+    bool lane_ok;
+    if (wave < R) {
+        row = wave;
+        c0 = lane * V;
+        lane_ok = true;
+    } else {
+        const int q = lane % (2 * NVH);
+        row = lane / (2 * NVH);
+        lane_ok = row < R;
+        if (!lane_ok)
+            row = 0;
+        c0 = q < NVH ? -HX + q * V : W + (q - NVH) * V;
+    }
+    const int ib = i0 + c0;
+    const int j = j0 - TS + row;
+    const bool act = lane_ok && j >= 0 && j < ny && ib >= 0 && ib < nx;
+    const bool own = wave < R && row >= TS && row < R - TS && act;
+    const bool full = ib + V <= nx;
+    const unsigned off = (unsigned)(ib + px * j) * (unsigned)sizeof(T);
+    const int lr = row + 1;     // LDS row
+    const int lc = HX + c0;     // LDS column of the first cell
+
+    const T *Ex = src.f[0], *Ey = src.f[1], *Ez = src.f[2];
+    const T *Hx = src.f[3], *Hy = src.f[4], *Hz = src.f[5];
+    const vec zero = (vec)(T)0;
+
+    // per-stage registers (index s-1)
+    vec Ecur[TS][3];   // E^{n+s-1}(p_s)
+    vec Hold[TS][3];   // H^{n+s-3/2}(p_s)
+    vec Hprv[TS][2];   // H^{n+s-1/2}(p_s - 1), x and y
+    vec Ce[TS][3];     // Ce(p_s)
+    vec Ch[TS][3];     // Ch(p_s)
+#pragma unroll
+    for (int s = 0; s < TS; ++s) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            Ecur[s][q] = zero;
+            Hold[s][q] = zero;
+            Ce[s][q] = (vec)c.ce_s;
+            Ch[s][q] = (vec)c.ch_s;
+        }
+        Hprv[s][0] = zero;
+        Hprv[s][1] = zero;
+    }
+    vec En1[3] = {zero, zero, zero};  // E^n(p_1 + 1)
+
+    const int k0 = max(0, kb - TS);
+    const int kend = ke + TS - 2;  // last loop index
+    // first planes of stage 1
+    if (act) {
+        const long long pk = (long long)k0 * P;
+        Ecur[0][0] = ld2(Ex + pk, off);
+        Ecur[0][1] = ld2(Ey + pk, off);
+        Ecur[0][2] = ld2(Ez + pk, off);
+        if (k0 + 1 < nz) {
+            En1[0] = ld2(Ex + pk + P, off);
+            En1[1] = ld2(Ey + pk + P, off);
+            En1[2] = ld2(Ez + pk + P, off);
+        }
+        Hold[0][0] = ld2(Hx + pk, off);
+        Hold[0][1] = ld2(Hy + pk, off);
+        Hold[0][2] = ld2(Hz + pk, off);
+        if (CE_ARR) {
+            Ce[0][0] = ld2(c.ce[0] + pk, off);
+            Ce[0][1] = ld2(c.ce[1] + pk, off);
+            Ce[0][2] = ld2(c.ce[2] + pk, off);
+        }
+        if (CH_ARR) {
+            Ch[0][0] = ld2(c.ch[0] + pk, off);
+            Ch[0][1] = ld2(c.ch[1] + pk, off);
+            Ch[0][2] = ld2(c.ch[2] + pk, off);
+        }
+    }
+    __syncthreads();  // LDS zeroing done
+
+    for (int k = k0; k <= kend; ++k) {
+        // ---------------- prefetch stage-1 inputs of plane k+1 ----------------
+        vec pE[3] = {zero, zero, zero}, pH[3] = {zero, zero, zero};
+        vec pCe[3] = {(vec)c.ce_s, (vec)c.ce_s, (vec)c.ce_s}, pCh[3] = {(vec)c.ch_s, (vec)c.ch_s, (vec)c.ch_s};
+        if (act && k + 1 <= kend && k + 1 < nz) {
+            const long long pk1 = (long long)(k + 1) * P;
+            if (k + 2 < nz) {
+                pE[0] = ld2(Ex + pk1 + P, off);
+                pE[1] = ld2(Ey + pk1 + P, off);
+                pE[2] = ld2(Ez + pk1 + P, off);
+            }
+            pH[0] = ld2(Hx + pk1, off);
+            pH[1] = ld2(Hy + pk1, off);
+            pH[2] = ld2(Hz + pk1, off);
+            if (CE_ARR) {
+                pCe[0] = ld2(c.ce[0] + pk1, off);
+                pCe[1] = ld2(c.ce[1] + pk1, off);
+                pCe[2] = ld2(c.ce[2] + pk1, off);
+            }
+            if (CH_ARR) {
+                pCh[0] = ld2(c.ch[0] + pk1, off);
+                pCh[1] = ld2(c.ch[1] + pk1, off);
+                pCh[2] = ld2(c.ch[2] + pk1, off);
+            }
+        }
+        // ---------------- stage the E input of every stage ----------------
+        if (lane_ok) {
+#pragma unroll
+            for (int s = 0; s < TS; ++s)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) *(vec *)&sE[s][q][lr][lc] = Ecur[s][q];
+        }
+        __syncthreads();
+
+        vec hout[TS][3];
+        vec eout[TS][3];
+#pragma unroll
+        for (int s = 0; s < TS; ++s) {
+            const int p = k - s;  // plane of stage s+1
+            const int lo = max(0, kb - TS + s), hi = min(nz - 1, ke + TS - 2 - s);
+            const bool live = p >= lo && p <= hi;
+            // ---- E update of the previous stage (its H was staged in the previous phase) ----
+            if (s > 0) {
+                const int sp = s - 1;
+                const int pp = k - sp;
+                const int lop = max(0, kb - TS + sp), hip = min(nz - 1, ke + TS - 2 - sp);
+                const bool livep = pp >= lop && pp <= hip;
+                const int hb = (sp + 1) & 1;
+                vec ex = Ecur[sp][0], ey = Ecur[sp][1], ez = Ecur[sp][2];
+                if (livep && act) {
+                    const vec hzj = *(const vec *)&sH[hb][2][lr - 1][lc];  // Hz(i, j-1)
+                    const vec hxj = *(const vec *)&sH[hb][0][lr - 1][lc];  // Hx(i, j-1)
+                    const T hzl = sH[hb][2][lr][lc - 1];                   // Hz(ib-1, j)
+                    const T hyl = sH[hb][1][lr][lc - 1];                   // Hy(ib-1, j)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const int i = ib + v;
+                        if (i >= nx)
+                            continue;
+                        const T hz_im = v > 0 ? hout[sp][2][v - 1] : hzl;
+                        const T hy_im = v > 0 ? hout[sp][1][v - 1] : hyl;
+                        if (j >= 1 && pp >= 1)
+                            ex[v] = curl_update(Ecur[sp][0][v], Ce[sp][0][v], hout[sp][2][v], hzj[v], hout[sp][1][v],
+                                                Hprv[sp][1][v]);
+                        if (i >= 1 && pp >= 1)
+                            ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], Hprv[sp][0][v],
+                                                hout[sp][2][v], hz_im);
+                        if (i >= 1 && j >= 1)
+                            ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
+                                                hxj[v]);
+                    }
+                }
+                if (!livep) {
+                    ex = zero;
+                    ey = zero;
+                    ez = zero;
+                }
+                eout[sp][0] = ex;
+                eout[sp][1] = ey;
+                eout[sp][2] = ez;
+            }
+            // ---- H update of stage s ----
+            const vec *en = s == 0 ? En1 : eout[s - 1];  // E input at plane p+1 (own column)
+            const int hb = (s + 1) & 1;
+            vec hx = Hold[s][0], hy = Hold[s][1], hz = Hold[s][2];
+            if (live && act) {
+                const vec ezj = *(const vec *)&sE[s][2][lr + 1][lc];  // Ez(i, j+1)
+                const vec exj = *(const vec *)&sE[s][0][lr + 1][lc];  // Ex(i, j+1)
+                const T ezr = sE[s][2][lr][lc + V];                    // Ez(ib+V, j)
+                const T eyr = sE[s][1][lr][lc + V];                    // Ey(ib+V, j)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int i = ib + v;
+                    if (i >= nx)
+                        continue;
+                    const T ez_ip = v + 1 < V ? Ecur[s][2][v + 1] : ezr;
+                    const T ey_ip = v + 1 < V ? Ecur[s][1][v + 1] : eyr;
+                    if (i >= 1)
+                        hx[v] = curl_update(Hold[s][0][v], Ch[s][0][v], en[1][v], Ecur[s][1][v], ezj[v],
+                                            Ecur[s][2][v]);
+                    if (j >= 1)
+                        hy[v] = curl_update(Hold[s][1][v], Ch[s][1][v], ez_ip, Ecur[s][2][v], en[0][v],
+                                            Ecur[s][0][v]);
+                    if (p >= 1)
+                        hz[v] = curl_update(Hold[s][2][v], Ch[s][2][v], exj[v], Ecur[s][0][v], ey_ip,
+                                            Ecur[s][1][v]);
+                }
+            }
+            hout[s][0] = hx;
+            hout[s][1] = hy;
+            hout[s][2] = hz;
+            if (lane_ok) {
+                *(vec *)&sH[hb][0][lr][lc] = hx;
+                *(vec *)&sH[hb][1][lr][lc] = hy;
+                *(vec *)&sH[hb][2][lr][lc] = hz;
+            }
+            __syncthreads();
+        }
+        // ---------------- E update of the last stage and the stores ----------------
+        {
+            constexpr int sp = TS - 1;
+            const int pp = k - sp;
+            const int lop = max(0, kb - 1), hip = ke - 1;
+            const bool livep = pp >= lop && pp <= hip;
+            const int hb = (sp + 1) & 1;
+            vec ex = Ecur[sp][0], ey = Ecur[sp][1], ez = Ecur[sp][2];
+            if (livep && act) {
+                const vec hzj = *(const vec *)&sH[hb][2][lr - 1][lc];
+                const vec hxj = *(const vec *)&sH[hb][0][lr - 1][lc];
+                const T hzl = sH[hb][2][lr][lc - 1];
+                const T hyl = sH[hb][1][lr][lc - 1];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int i = ib + v;
+                    if (i >= nx)
+                        continue;
+                    const T hz_im = v > 0 ? hout[sp][2][v - 1] : hzl;
+                    const T hy_im = v > 0 ? hout[sp][1][v - 1] : hyl;
+                    if (j >= 1 && pp >= 1)
+                        ex[v] = curl_update(Ecur[sp][0][v], Ce[sp][0][v], hout[sp][2][v], hzj[v], hout[sp][1][v],
+                                            Hprv[sp][1][v]);
+                    if (i >= 1 && pp >= 1)
+                        ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], Hprv[sp][0][v],
+                                            hout[sp][2][v], hz_im);
+                    if (i >= 1 && j >= 1)
+                        ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
+                                            hxj[v]);
+                }
+                if (own && pp >= kb) {
+                    const long long pk = (long long)pp * P;
+                    if (full) {
+                        st2(dst.f[0] + pk, off, ex);
+                        st2(dst.f[1] + pk, off, ey);
+                        st2(dst.f[2] + pk, off, ez);
+                        st2(dst.f[3] + pk, off, hout[sp][0]);
+                        st2(dst.f[4] + pk, off, hout[sp][1]);
+                        st2(dst.f[5] + pk, off, hout[sp][2]);
+                    } else {
+                        // V = 2: only the first cell is in the domain
+                        st1(dst.f[0] + pk, off, ex[0]);
+                        st1(dst.f[1] + pk, off, ey[0]);
+                        st1(dst.f[2] + pk, off, ez[0]);
+                        st1(dst.f[3] + pk, off, hout[sp][0][0]);
+                        st1(dst.f[4] + pk, off, hout[sp][1][0]);
+                        st1(dst.f[5] + pk, off, hout[sp][2][0]);
+                    }
+                }
+            }
+            eout[sp][0] = ex;
+            eout[sp][1] = ey;
+            eout[sp][2] = ez;
+        }
+        // ---------------- rotate: stage s feeds stage s+1 at the next plane ----------------
+#pragma unroll
+        for (int s = TS - 1; s >= 0; --s) {
+            Hprv[s][0] = hout[s][0];
+            Hprv[s][1] = hout[s][1];
+            if (s + 1 < TS) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    Ecur[s + 1][q] = eout[s][q];
+                    Hold[s + 1][q] = hout[s][q];
+                    if (CE_ARR)
+                        Ce[s + 1][q] = Ce[s][q];
+                    if (CH_ARR)
+                        Ch[s + 1][q] = Ch[s][q];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            Ecur[0][q] = En1[q];
+            En1[q] = pE[q];
+            Hold[0][q] = pH[q];
+            if (CE_ARR)
+                Ce[0][q] = pCe[q];
+            if (CH_ARR)
+                Ch[0][q] = pCh[q];
+        }
+    }
+}
+
+template <typename T, int TS>
+hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c, int zchunk,
+                     hipStream_t s)
+{
+    constexpr int W = 128, R = 15;
+    const int kchunk = (g.nz + zchunk - 1) / zchunk;
+    const int nzc = (g.nz + kchunk - 1) / kchunk;
+    const int ntx = (g.nx + W - 1) / W, nty = (g.ny + (R - 2 * TS) - 1) / (R - 2 * TS);
+    const int ntiles = ntx * nty * nzc;
+    const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
+    dim3 block(64, R + 1), grid(nblocks);
+    const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
+    if (cea && cha)
+        hipLaunchKernelGGL((k_temporal<T, TS, true, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+                           ntiles);
+    else if (cea)
+        hipLaunchKernelGGL((k_temporal<T, TS, true, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+                           ntiles);
+    else if (cha)
+        hipLaunchKernelGGL((k_temporal<T, TS, false, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+                           ntiles);
+    else
+        hipLaunchKernelGGL((k_temporal<T, TS, false, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+                           ntiles);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int temporal_own_rows(int ts) { return 15 - 2 * ts; }
+
+template <typename T>
+hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c,
+                                int zchunk, int ts, hipStream_t s)
+{
+    zchunk = zchunk < 1 ? 1 : zchunk;
+    switch (ts) {
+    case 1: return launch_ts<T, 1>(g, src, dst, c, zchunk, s);
+    case 2: return launch_ts<T, 2>(g, src, dst, c, zchunk, s);
+    case 3: return launch_ts<T, 3>(g, src, dst, c, zchunk, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_temporal_step<float>(const Geom &, const Fields<float> &, const Fields<float> &,
+                                                const Coefs<float> &, int, int, hipStream_t);
+
+}  // namespace fdtd
+
+namespace fdtd {
+
+// FP64 storage has no temporal kernel (its LDS tiles would not fit); create rejects it.
+template <>
+hipError_t launch_temporal_step<double>(const Geom &, const Fields<double> &, const Fields<double> &,
+                                        const Coefs<double> &, int, int, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+}  // namespace fdtd

@@ -49,8 +49,9 @@ def oracle_reference(nx, ny, nz, e_init, h_init, eps, mu, steps, storage=np.floa
     return ref
 
 
-def run_gpu(nx, ny, nz, e_init, h_init, eps, mu, steps, kernel="auto", storage="f32", dt=S):
-    with _solver(nx, ny, nz, 1.0, dt, eps_r=eps, mu_r=mu, kernel=kernel, storage=storage) as s:
+def run_gpu(nx, ny, nz, e_init, h_init, eps, mu, steps, kernel="auto", storage="f32", dt=S, tb_steps=0):
+    with _solver(nx, ny, nz, 1.0, dt, eps_r=eps, mu_r=mu, kernel=kernel, storage=storage,
+                 tb_steps=tb_steps) as s:
         s.set_fields(e_init, h_init)
         s.step(steps)
         out = s.get_fields()
@@ -154,10 +155,34 @@ def test_kernels_bitwise_equal(monkeypatch):
             else:
                 monkeypatch.setenv(name, val)
         outs[(kernel, zc, var)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel)
+    for tb in (1, 2, 3):
+        for tzc in ("1", "2", "5"):
+            monkeypatch.setenv("FDTD_TZCHUNKS", tzc)
+            outs[("temporal", tb, tzc)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel="temporal",
+                                                  tb_steps=tb)
     base = outs[("plain", None, None)]
     for key, out in outs.items():
         for a, b in zip(out, base):
             assert np.array_equal(a, b), key
+
+
+@pytest.mark.parametrize("tb", [1, 2, 3])
+def test_temporal_parity_ragged(tb):
+    # odd step count: tb-step sweeps plus single-step remainder
+    nx, ny, nz, steps = 133, 40, 71, 301
+    eps = ci.sphere_eps(nx, ny, nz, seed=34, nspheres=10)
+    mu = ci.uniform_cell_eps(nx, ny, nz, seed=10, lo=1.0, hi=1.5)
+    e = ci.random_e(nx, ny, nz, seed=11, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=12, dtype=np.float32)
+    got = run_gpu(nx, ny, nz, e, h, eps, mu, steps, kernel="temporal", tb_steps=tb)
+    ref = oracle_reference(nx, ny, nz, e, h, eps, mu, steps)
+    err = rel_l2(got, ref)
+    print(f"\n{nx}x{ny}x{nz} temporal tb={tb}: rel-L2 = {err:.3e}")
+    assert err < 1e-5
+    assert oracle.tangential_max(got) == 0.0
+    plain = run_gpu(nx, ny, nz, e, h, eps, mu, steps, kernel="plain")
+    for a, b in zip(got, plain):
+        assert np.array_equal(a.astype(np.float32), b.astype(np.float32))
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
