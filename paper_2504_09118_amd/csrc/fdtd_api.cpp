@@ -195,11 +195,12 @@ int scan_material(const double *m, size_t n, double *mn, const char *name)
     return FDTD_OK;
 }
 
+// The fastest schedule measured on MI355X for each storage type: FP32 runs
+// the temporal sweep (3 steps per HBM pass), FP64 the single-step slab.
 int resolve_kernel(int kernel, int storage)
 {
-    (void)storage;
     if (kernel == FDTD_KERNEL_AUTO)
-        return FDTD_KERNEL_SLAB;
+        return storage == FDTD_F32 ? FDTD_KERNEL_TEMPORAL : FDTD_KERNEL_SLAB;
     return kernel;
 }
 
@@ -417,7 +418,7 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     if (kern == FDTD_KERNEL_TEMPORAL && o->storage != FDTD_F32)
         return fail(FDTD_E_UNSUPPORTED, "the temporal kernel is built for FP32 storage only");
     if (kern == FDTD_KERNEL_TEMPORAL && (o->tb_steps < 0 || o->tb_steps > 3))
-        return fail(FDTD_E_ARG, "tb_steps must be 1..3 (0: default 2), got %d", o->tb_steps);
+        return fail(FDTD_E_ARG, "tb_steps must be 1..3 (0: default 3), got %d", o->tb_steps);
     if (o->arena && o->arena_bytes == 0)
         return fail(FDTD_E_ARG, "arena given with arena_bytes = 0");
     const double *eps = coef ? coef->eps_r : nullptr;
@@ -449,7 +450,7 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     h->dt = dt;
     h->storage = o->storage;
     h->kernel = kern;
-    h->tb = kern == FDTD_KERNEL_TEMPORAL ? (o->tb_steps > 0 ? o->tb_steps : 2) : 1;
+    h->tb = kern == FDTD_KERNEL_TEMPORAL ? (o->tb_steps > 0 ? o->tb_steps : 3) : 1;
     h->device = o->device;
     h->zchunk = env_int("FDTD_ZCHUNKS", 0);
     h->variant = env_int("FDTD_SLAB_VARIANT", 0);
