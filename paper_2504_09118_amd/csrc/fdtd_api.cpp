@@ -112,7 +112,7 @@ struct fdtd_solver {
     uint32_t magic;
     int nx, ny, nz;
     double dx, dt;
-    int storage, kernel, tb, device, zchunk, tzchunk, variant;
+    int storage, kernel, tb, device, zchunk, tzchunk, variant, tvariant;
     hipStream_t stream;
     bool own_stream;
     char *arena;
@@ -224,7 +224,7 @@ hipError_t launch_one(fdtd_t h, int kernel, int ts)
                                       h->variant, h->stream);
     else if (kernel == FDTD_KERNEL_TEMPORAL)
         e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                          h->tzchunk, ts, h->stream);
+                                          h->tzchunk, ts, h->tvariant, h->stream);
     else
         e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c, h->zchunk,
                                        h->stream);
@@ -476,13 +476,15 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         while (tiles * zc < target && nz / (zc * 2) >= 16) zc *= 2;
         h->zchunk = zc;
     }
+    h->tvariant = env_int("FDTD_TEMPORAL_VARIANT", 0);
     h->tzchunk = env_int("FDTD_TZCHUNKS", 0);
     if (h->tzchunk <= 0) {
         // temporal sweeps redo 2*tb-1 planes per z-chunk: keep chunks >= 48 planes
-        const int own = fdtd::temporal_own_rows(h->tb);
-        const long long tiles = (long long)((nx + 127) / 128) * ((ny + own - 1) / own);
+        const int own = fdtd::temporal_own_rows(h->tb, h->tvariant);
+        const int w = fdtd::temporal_width(h->tvariant);
+        const long long tiles = (long long)((nx + w - 1) / w) * ((ny + own - 1) / own);
         int zc = 1;
-        while (tiles * zc < 1024 && nz / (zc * 2) >= 48) zc *= 2;
+        while (tiles * zc < 768 && nz / (zc * 2) >= 48) zc *= 2;
         h->tzchunk = zc;
     }
     if (o->stream) {

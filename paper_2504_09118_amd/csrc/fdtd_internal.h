@@ -74,8 +74,9 @@ hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T>
 // Built for FP32 storage only.
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
-                                const Coefs<T> &c, int zchunk, int ts, hipStream_t s);
-int temporal_own_rows(int ts);
+                                const Coefs<T> &c, int zchunk, int ts, int variant, hipStream_t s);
+int temporal_own_rows(int ts, int variant);
+int temporal_width(int variant);
 
 // Tile rows owned per workgroup (rows - 2) and tile width of a slab variant.
 int slab_rows(int variant);

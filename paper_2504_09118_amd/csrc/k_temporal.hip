@@ -4,8 +4,9 @@
 // here one z-marching sweep advances the state by TS steps, so the six
 // components and the coefficients cross HBM once per TS steps.
 //
-// Structure (per workgroup: an x-y tile of 64V own columns x (R - 2 TS) own
-// rows, marching a z-chunk):
+// Structure (per workgroup of 16 waves: an x-y tile of W own columns x
+// (R - 2 TS) own rows, marching a z-chunk; the default tile is 64 x 26 for
+// TS = 2, 64 x 22 for TS = 3):
 //   - stage s = 1..TS computes step n+s on plane p_s = k - (s-1) at loop
 //     index k: H^{n+s-1/2}(p_s) from E^{n+s-1} at planes p_s and p_s+1, then
 //     E^{n+s}(p_s) from H^{n+s-1/2} at planes p_s and p_s-1. Stage s-1 has
@@ -68,15 +69,28 @@ __device__ __forceinline__ void st1(T *plane, unsigned boff, T x)
     *(FDTD_GLOBAL T *)(uni(plane) + boff) = x;
 }
 
-template <typename T, int TS, bool CE_ARR, bool CH_ARR>
+// Workgroup shape of the temporal sweep: 16 waves; RPW rows per wave
+// (64/RPW lanes per row, 2 cells per lane); the last NHW waves hold the
+// x-halo vectors of all rows.
+template <int TS, int RPW>
+struct TShape {
+    static constexpr int V = 2;                          // cells per lane (x)
+    static constexpr int LPR = 64 / RPW;                 // lanes per row
+    static constexpr int W = LPR * V;                    // own columns
+    static constexpr int NVH = (TS + V - 1) / V;         // halo vectors per side
+    static constexpr int HX = NVH * V;                   // halo columns per side
+    static constexpr int NHW = (RPW == 2 && TS == 3) ? 2 : 1;  // halo waves
+    static constexpr int NRW = 16 - NHW;                 // row waves
+    static constexpr int R = NRW * RPW;                  // rows (own rows: R - 2 TS)
+    static_assert(2 * NVH * R <= 64 * NHW, "halo lanes do not fit");
+};
+
+template <typename T, int TS, int RPW, bool CE_ARR, bool CH_ARR>
 __global__ void __launch_bounds__(1024)
     k_temporal(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles)
 {
-    constexpr int V = 2;                    // cells per lane (x)
-    constexpr int R = 15;                   // row waves; wave R holds the x-halo
-    constexpr int W = 64 * V;               // own columns
-    constexpr int NVH = (TS + V - 1) / V;   // halo vectors per side
-    constexpr int HX = NVH * V;             // halo columns per side
+    using S = TShape<TS, RPW>;
+    constexpr int V = S::V, W = S::W, NVH = S::NVH, HX = S::HX, R = S::R, NRW = S::NRW, LPR = S::LPR;
     constexpr int LP = HX + W + HX + V;     // LDS row pitch (one pad vector at the end)
     constexpr int RB = R + 2;               // LDS rows (one pad row each side)
     using vec = typename V2<T>::type;
@@ -105,21 +119,23 @@ __global__ void __launch_bounds__(1024)
         T *flatE = &sE[0][0][0][0];
         T *flatH = &sH[0][0][0][0];
         const int tid = threadIdx.y * 64 + threadIdx.x;
-        for (int q = tid; q < TS * 3 * RB * LP; q += 64 * (R + 1)) flatE[q] = 0;
-        for (int q = tid; q < 2 * 3 * RB * LP; q += 64 * (R + 1)) flatH[q] = 0;
+        for (int q = tid; q < TS * 3 * RB * LP; q += 1024) flatE[q] = 0;
+        for (int q = tid; q < 2 * 3 * RB * LP; q += 1024) flatH[q] = 0;
     }
 
     // lane geometry: (row, first local column c0) of the lane's V cells
     const int wave = threadIdx.y, lane = threadIdx.x;
     int row, c0;
     bool lane_ok;
-    if (wave < R) {
-        row = wave;
-        c0 = lane * V;
+    const bool main_wave = wave < NRW;
+    if (main_wave) {
+        row = wave * RPW + lane / LPR;
+        c0 = (lane % LPR) * V;
         lane_ok = true;
     } else {
-        const int q = lane % (2 * NVH);
-        row = lane / (2 * NVH);
+        const int L = (wave - NRW) * 64 + lane;
+        const int q = L % (2 * NVH);
+        row = L / (2 * NVH);
         lane_ok = row < R;
         if (!lane_ok)
             row = 0;
@@ -128,7 +144,7 @@ __global__ void __launch_bounds__(1024)
     const int ib = i0 + c0;
     const int j = j0 - TS + row;
     const bool act = lane_ok && j >= 0 && j < ny && ib >= 0 && ib < nx;
-    const bool own = wave < R && row >= TS && row < R - TS && act;
+    const bool own = main_wave && row >= TS && row < R - TS && act;
     const bool full = ib + V <= nx;
     const unsigned off = (unsigned)(ib + px * j) * (unsigned)sizeof(T);
     const int lr = row + 1;     // LDS row
@@ -389,52 +405,67 @@ __global__ void __launch_bounds__(1024)
     }
 }
 
-template <typename T, int TS>
+template <typename T, int TS, int RPW>
 hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c, int zchunk,
                      hipStream_t s)
 {
-    constexpr int W = 128, R = 15;
+    using S = TShape<TS, RPW>;
     const int kchunk = (g.nz + zchunk - 1) / zchunk;
     const int nzc = (g.nz + kchunk - 1) / kchunk;
-    const int ntx = (g.nx + W - 1) / W, nty = (g.ny + (R - 2 * TS) - 1) / (R - 2 * TS);
+    const int own = S::R - 2 * TS;
+    const int ntx = (g.nx + S::W - 1) / S::W, nty = (g.ny + own - 1) / own;
     const int ntiles = ntx * nty * nzc;
     const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
-    dim3 block(64, R + 1), grid(nblocks);
+    dim3 block(64, 16), grid(nblocks);
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
     if (cea && cha)
-        hipLaunchKernelGGL((k_temporal<T, TS, true, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+        hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
                            ntiles);
     else if (cea)
-        hipLaunchKernelGGL((k_temporal<T, TS, true, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles);
+        hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
+                           nty, ntiles);
     else if (cha)
-        hipLaunchKernelGGL((k_temporal<T, TS, false, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles);
+        hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
+                           nty, ntiles);
     else
-        hipLaunchKernelGGL((k_temporal<T, TS, false, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles);
+        hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
+                           nty, ntiles);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int temporal_own_rows(int ts) { return 15 - 2 * ts; }
+// variant 0: two rows per wave (64 x ~26 tiles); variant 1: one row per wave (128 x ~11 tiles)
+int temporal_own_rows(int ts, int variant)
+{
+    return variant == 1 ? 15 - 2 * ts : (ts == 3 ? 28 : 30) - 2 * ts;
+}
+
+int temporal_width(int variant) { return variant == 1 ? 128 : 64; }
 
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c,
-                                int zchunk, int ts, hipStream_t s)
+                                int zchunk, int ts, int variant, hipStream_t s)
 {
     zchunk = zchunk < 1 ? 1 : zchunk;
+    if (variant == 1) {
+        switch (ts) {
+        case 1: return launch_ts<T, 1, 1>(g, src, dst, c, zchunk, s);
+        case 2: return launch_ts<T, 2, 1>(g, src, dst, c, zchunk, s);
+        case 3: return launch_ts<T, 3, 1>(g, src, dst, c, zchunk, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (ts) {
-    case 1: return launch_ts<T, 1>(g, src, dst, c, zchunk, s);
-    case 2: return launch_ts<T, 2>(g, src, dst, c, zchunk, s);
-    case 3: return launch_ts<T, 3>(g, src, dst, c, zchunk, s);
+    case 1: return launch_ts<T, 1, 2>(g, src, dst, c, zchunk, s);
+    case 2: return launch_ts<T, 2, 2>(g, src, dst, c, zchunk, s);
+    case 3: return launch_ts<T, 3, 2>(g, src, dst, c, zchunk, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template hipError_t launch_temporal_step<float>(const Geom &, const Fields<float> &, const Fields<float> &,
-                                                const Coefs<float> &, int, int, hipStream_t);
+                                                const Coefs<float> &, int, int, int, hipStream_t);
 
 }  // namespace fdtd
 
@@ -443,7 +474,7 @@ namespace fdtd {
 // FP64 storage has no temporal kernel (its LDS tiles would not fit); create rejects it.
 template <>
 hipError_t launch_temporal_step<double>(const Geom &, const Fields<double> &, const Fields<double> &,
-                                        const Coefs<double> &, int, int, hipStream_t)
+                                        const Coefs<double> &, int, int, int, hipStream_t)
 {
     return hipErrorNotSupported;
 }

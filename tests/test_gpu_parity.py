@@ -155,11 +155,13 @@ def test_kernels_bitwise_equal(monkeypatch):
             else:
                 monkeypatch.setenv(name, val)
         outs[(kernel, zc, var)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel)
-    for tb in (1, 2, 3):
-        for tzc in ("1", "2", "5"):
-            monkeypatch.setenv("FDTD_TZCHUNKS", tzc)
-            outs[("temporal", tb, tzc)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel="temporal",
-                                                  tb_steps=tb)
+    for tv in ("0", "1"):
+        monkeypatch.setenv("FDTD_TEMPORAL_VARIANT", tv)
+        for tb in (1, 2, 3):
+            for tzc in ("1", "2", "5"):
+                monkeypatch.setenv("FDTD_TZCHUNKS", tzc)
+                outs[("temporal", tv, tb, tzc)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel="temporal",
+                                                          tb_steps=tb)
     base = outs[("plain", None, None)]
     for key, out in outs.items():
         for a, b in zip(out, base):
