@@ -13,6 +13,7 @@ timed on the host on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -38,6 +39,30 @@ def algorithmic_bytes_per_cell_step(kernel: str, ce_arrays: bool, ch_arrays: boo
     if kernel == "plain":
         return (18 + coef) * esz
     return (12 + coef) * esz
+
+
+def recorded_traffic(kernel: str, steps_per_sweep: int, n: int):
+    """HBM bytes per launch measured with rocprofv3 for this kernel, if its source is unchanged.
+
+    profiles/traffic_records.txt lists copy-probe-calibrated FETCH_SIZE + WRITE_SIZE
+    bytes per dispatch together with the sha256 of the kernel source at capture;
+    a changed source makes the record stale and the traffic unknown (None).
+    """
+    path = os.path.join(ROOT, "profiles", "traffic_records.txt")
+    if not os.path.exists(path):
+        return None, None
+    for line in open(path):
+        parts = line.split()
+        if not parts or parts[0].startswith("#") or len(parts) != 8:
+            continue
+        k, tb, nn, src, sha, rd, wr, summary = parts
+        if k != kernel or int(tb) != steps_per_sweep or int(nn) != n:
+            continue
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None, None
+        return int(rd) + int(wr), summary
+    return None, None
 
 
 def main() -> int:
@@ -110,6 +135,9 @@ def main() -> int:
     b_sweep = algorithmic_bytes_per_cell_step(kernel, q["ce_array"], q["ch_array"])
     bytes_per_launch = b_sweep * cells / launches_per_sweep
     achieved = bytes_per_launch * launches / secs / 1e9
+    traffic, traffic_src = (None, None)
+    if nx == ny == nz:
+        traffic, traffic_src = recorded_traffic(kernel, steps_per_launch, nx)
 
     result = {
         "metric": "Gcell-updates/s (512^3 FP32 PEC cavity, spherical eps inclusions)",
@@ -128,7 +156,8 @@ def main() -> int:
                                f"scalar Ch, Courant 0.5/sqrt(3)",
                    "kernel": kernel, "steps_per_launch": steps_per_launch, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "bytes_per_cell_step": round(b_sweep / steps_per_launch, 3),
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": round(avg_launch_s * 1e3, 5),

@@ -13,7 +13,7 @@ state" of a cavity, Sec. 1 Fig. 1b and Sec. 4):
   Ex (nx, ny+1, nz+1), Ey (nx+1, ny, nz+1), Ez (nx+1, ny+1, nz),
   Hx (nx+1, ny, nz), Hy (nx, ny+1, nz), Hz (nx, ny, nz+1)   [given as (x, y, z)].
   These are the only extents under which the slicing form of the curl
-  (Sec. 2.2, NumPy listing of curl_Hx) broadcasts.
+  (Sec. 2.1, NumPy listing of curl_Hx) broadcasts.
 * Random draws come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
   pseudorandom number generators", OOPSLA 2014), used counter-style: the c-th
   output for seed s is mix64(s + (c + 1) * 0x9E3779B97F4A7C15 mod 2^64), the

@@ -5,12 +5,12 @@
  * Yee leapfrog (He, Andersson, Markidis, "Optimizing FDTD Solvers for
  * Electromagnetics: A Compiler-Guided Approach with High-Level Tensor
  * Abstractions", arXiv 2504.09118):
- *   - Sec. 2.1, Eq. 2: the six component updates; E uses dt/eps, H uses
+ *   - Sec. 2, Eq. 2: the six component updates; E uses dt/eps, H uses
  *     dt/mu, with the minus sign of Faraday's law as printed in Eq. 2.
- *   - Sec. 2.2, full algorithm listing: each step updates H from the curl
+ *   - Sec. 2.1, full algorithm listing: each step updates H from the curl
  *     of E, applies the H boundary, updates E from the curl of H, applies the
  *     E boundary.
- *   - Sec. 2.2, naive and slicing curl_Hx listings: forward differences of E
+ *   - Sec. 2.1, naive and slicing curl_Hx listings: forward differences of E
  *     for H, staggered array extents.
  *   - Fig. 1b caption and Sec. 4: PEC walls on a box cavity.
  *
@@ -134,7 +134,7 @@ int fdtd_set_fields(fdtd_t h, const void *const host[6], int host_dtype);
 int fdtd_set_fields_device(fdtd_t h, const void *const dev[6], int dev_dtype);
 
 /*
- * Enqueue n >= 0 leapfrog steps (Sec. 2.2 algorithm listing: H update, H
+ * Enqueue n >= 0 leapfrog steps (Sec. 2.1 algorithm listing: H update, H
  * boundary, E update, E boundary). Asynchronous: returns after launching.
  * Launch failures return FDTD_E_DEVICE at once; faults during execution
  * surface at the next fdtd_sync / fdtd_get_fields.

@@ -8,9 +8,9 @@ nothing from the product.
 Two independent implementations of the same definition:
 
 * ``yee_oracle.c`` (plain C loops, FP64, loaded through ctypes) is the oracle.
-  Its loops follow the naive curl_Hx listing of Sec. 2.2 and Eq. 2.
+  Its loops follow the naive curl_Hx listing of Sec. 2.1 and Eq. 2.
 * ``numpy_form.py`` is the whole-array slicing form of the NumPy curl_Hx
-  listing (Sec. 2.2), the paper's own baseline; it cross-checks the C oracle.
+  listing (Sec. 2.1), the paper's own baseline; it cross-checks the C oracle.
 
 Arrays are NumPy float64, C-order, shape (Z, Y, X) indexed [k, j, i] with the
 staggered extents listed in ``cavity_inputs.field_shapes``.

@@ -1,7 +1,7 @@
 """Second, independent FP64 implementation: the whole-array slicing form.
 
 TEST INFRASTRUCTURE (see the package docstring). This is the form of the
-paper's NumPy curl_Hx listing (Sec. 2.2), the paper's own baseline (Sec. 4),
+paper's NumPy curl_Hx listing (Sec. 2.1), the paper's own baseline (Sec. 4),
 extended to all six components and to per-node coefficient arrays. Arrays
 are (Z, Y, X) = [k, j, i]; the slice shapes only broadcast under the
 staggered extents, which is what fixes those extents.
@@ -57,7 +57,7 @@ def curl_e(fields, ce, ch=None, mutation=None):
 
 
 def run(fields, ce, ch, nsteps: int, mutation=None) -> None:
-    """The full algorithm listing of Sec. 2.2: per step curl H, H edge (nothing), curl E, E edge."""
+    """The full algorithm listing of Sec. 2.1: per step curl H, H edge (nothing), curl E, E edge."""
     for _ in range(int(nsteps)):
         curl_h(fields, ch, mutation)
         curl_e(fields, ce, ch, mutation)

@@ -6,7 +6,7 @@
  * smoke check and the CPU-baseline leg of the benchmark may load it. It shares
  * no code, header, table or helper with the HIP library.
  *
- * What it computes (paper, Sec. 2.1 Eq. 2, and Sec. 2.2 with the full
+ * What it computes (paper, Sec. 2 Eq. 2, and Sec. 2.1 with the full
  * algorithm listing and the naive / slicing curl_Hx listings):
  *   each time step = update H from the curl of E (all H nodes), then update E
  *   from the curl of the new H (interior E nodes); tangential E on the six

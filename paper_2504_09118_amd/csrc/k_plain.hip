@@ -2,7 +2,7 @@
 //   sweep 1: update every H node from the curl of E   (Eq. 2 right column)
 //   sweep 2: update every interior E node from the curl of the new H
 //            (Eq. 2 left column, J = 0)
-// This is the algorithm listing of Sec. 2.2 with the three curl_H (curl_E)
+// This is the algorithm listing of Sec. 2.1 with the three curl_H (curl_E)
 // calls of a half-step merged into one pass; the H boundary needs no work and
 // the E boundary (PEC) is the set of nodes sweep 2 never writes.
 // Bytes per cell-step (FP32, per-node Ce): sweep 1 reads E, reads and writes

@@ -1,7 +1,7 @@
 // The single arithmetic form of one Yee component update, shared by every
 // kernel schedule so that all schedules produce the same bits.
 //
-// Eq. 2 (Sec. 2.1) with cubic cells: a component f advances by its
+// Eq. 2 (Sec. 2) with cubic cells: a component f advances by its
 // coefficient (dt/eps or dt/mu, with 1/dx folded in) times the difference of
 // two staggered one-cell differences:
 //   f_new = f + c * ((a1 - a0) - (b1 - b0))

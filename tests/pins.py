@@ -4,7 +4,7 @@ Each function takes ``run(fields, ce, ch, nsteps)``, a stepper that advances
 a 6-tuple of FP64 arrays in place, so the same checks apply to the C oracle,
 to its NumPy slicing form, and to deliberately broken variants. None of them
 re-types the stepper's formula: the expected values come from the discrete
-dispersion relation derived from Eq. 2 (Sec. 2.1), from the structure of the
+dispersion relation derived from Eq. 2 (Sec. 2), from the structure of the
 scheme (exact energy, divergence) or from symmetry.
 """
 
