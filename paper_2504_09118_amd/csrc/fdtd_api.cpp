@@ -23,6 +23,17 @@
 #include "fdtd.h"
 #include "fdtd_internal.h"
 
+namespace fdtd {
+int xcd_remap()
+{
+    static const int v = [] {
+        const char *e = getenv("FDTD_XCD_REMAP");
+        return (e && *e) ? (atoi(e) != 0) : 1;
+    }();
+    return v;
+}
+}  // namespace fdtd
+
 using fdtd::Coefs;
 using fdtd::Fields;
 using fdtd::Geom;

@@ -104,6 +104,10 @@ template <typename T>
 hipError_t launch_diag(const Geom &g, const Fields<T> &f, const Coefs<T> &c, double *partial,
                        double *out_dev, hipStream_t s);
 
+// Whether the tiled sweeps number their workgroups for the 8 XCDs (1, the
+// default) or in plain launch order (0); FDTD_XCD_REMAP=0 selects the latter.
+int xcd_remap();
+
 // Staggered extents (X, Y, Z) of field f in 0..5.
 __host__ __device__ inline void extents(const Geom &g, int f, int &X, int &Y, int &Z)
 {

@@ -99,7 +99,8 @@ __device__ __forceinline__ void st1(T *plane, unsigned boff, T x)
 
 template <typename T, int V, int R, bool CE_ARR, bool CH_ARR>
 __global__ void __launch_bounds__(64 * R)
-    k_slab(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles)
+    k_slab(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles,
+               int xcd_remap)
 {
     using vec = typename VecOf<T, V>::type;
     constexpr int TX = 64 * V;       // tile width (cells)
@@ -112,7 +113,7 @@ __global__ void __launch_bounds__(64 * R)
     // XCD-aware tile numbering: hardware block b runs on XCD b % 8.
     const int nper = (ntiles + kXcds - 1) / kXcds;
     const int b = blockIdx.x;
-    const int t = (b % kXcds) * nper + b / kXcds;
+    const int t = xcd_remap ? (b % kXcds) * nper + b / kXcds : b;
     if (t >= ntiles)
         return;  // the whole workgroup leaves before any barrier
     const int tile_x = t % ntx;
@@ -400,16 +401,16 @@ hipError_t launch_cfg(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
     if (cea && cha)
         hipLaunchKernelGGL((k_slab<T, V, R, true, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles);
+                           ntiles, xcd_remap());
     else if (cea)
         hipLaunchKernelGGL((k_slab<T, V, R, true, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles);
+                           ntiles, xcd_remap());
     else if (cha)
         hipLaunchKernelGGL((k_slab<T, V, R, false, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles);
+                           ntiles, xcd_remap());
     else
         hipLaunchKernelGGL((k_slab<T, V, R, false, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles);
+                           ntiles, xcd_remap());
     return hipGetLastError();
 }
 

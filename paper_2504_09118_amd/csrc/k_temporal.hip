@@ -87,7 +87,8 @@ struct TShape {
 
 template <typename T, int TS, int RPW, bool CE_ARR, bool CH_ARR>
 __global__ void __launch_bounds__(1024)
-    k_temporal(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles)
+    k_temporal(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles,
+               int xcd_remap)
 {
     using S = TShape<TS, RPW>;
     constexpr int V = S::V, W = S::W, NVH = S::NVH, HX = S::HX, R = S::R, NRW = S::NRW, LPR = S::LPR;
@@ -99,7 +100,7 @@ __global__ void __launch_bounds__(1024)
 
     const int nper = (ntiles + kXcds - 1) / kXcds;
     const int b = blockIdx.x;
-    const int t = (b % kXcds) * nper + b / kXcds;
+    const int t = xcd_remap ? (b % kXcds) * nper + b / kXcds : b;
     if (t >= ntiles)
         return;  // the whole workgroup leaves before any barrier
     const int tile_x = t % ntx;
@@ -420,16 +421,16 @@ hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst, 
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
     if (cea && cha)
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles);
+                           ntiles, xcd_remap());
     else if (cea)
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
-                           nty, ntiles);
+                           nty, ntiles, xcd_remap());
     else if (cha)
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
-                           nty, ntiles);
+                           nty, ntiles, xcd_remap());
     else
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
-                           nty, ntiles);
+                           nty, ntiles, xcd_remap());
     return hipGetLastError();
 }
 
