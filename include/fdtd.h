@@ -58,8 +58,14 @@ typedef enum {
     FDTD_E_UNSUPPORTED = -6   /* option combination not built */
 } fdtd_status;
 
-/* Element types of host or device buffers and of the device field storage. */
-typedef enum { FDTD_F64 = 0, FDTD_F32 = 1 } fdtd_dtype;
+/*
+ * Element types. Host and device buffers passed to set/get calls are FDTD_F64
+ * or FDTD_F32. Device field storage may also be 16-bit: FDTD_F16 (IEEE half)
+ * or FDTD_BF16 (bfloat16); such fields are widened to FP32 on load, a sweep
+ * computes in FP32 (coefficients stay FP32) and rounds to nearest even once
+ * when it stores, i.e. once per sweep of tb_steps steps.
+ */
+typedef enum { FDTD_F64 = 0, FDTD_F32 = 1, FDTD_F16 = 2, FDTD_BF16 = 3 } fdtd_dtype;
 
 /* Field indices in the six-pointer arrays. */
 enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ };
@@ -88,7 +94,8 @@ typedef struct {
 } fdtd_coef;
 
 typedef struct {
-    int storage;        /* fdtd_dtype of device fields: FDTD_F32 (default) or FDTD_F64 */
+    int storage;        /* fdtd_dtype of device fields: FDTD_F32 (default), FDTD_F64, FDTD_F16, FDTD_BF16
+                           (16-bit storage runs the temporal kernel only) */
     int kernel;         /* fdtd_kernel, default FDTD_KERNEL_AUTO */
     int tb_steps;       /* steps per sweep for FDTD_KERNEL_TEMPORAL (0: library default) */
     int device;         /* HIP device ordinal, default 0 */

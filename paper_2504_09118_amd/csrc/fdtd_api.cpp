@@ -71,8 +71,8 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Plan {
     Geom g;
-    size_t esz;
-    size_t box_bytes;
+    size_t fesz, cesz;             // bytes per field element, per coefficient element
+    size_t fbox_bytes, cbox_bytes;
     size_t off_fields[2][6];
     size_t off_ce[3], off_ch[3];
     size_t off_staging, staging_bytes;
@@ -92,21 +92,23 @@ Plan make_plan(int nx, int ny, int nz, int storage, bool ce_arr, bool ch_arr)
     g.pz = nz + 1;
     g.plane = (long long)g.px * g.py;
     g.box = (long long)round_up((size_t)g.plane * g.pz + 2 * fdtd::kGuardElems, 64);
-    p.esz = storage == FDTD_F64 ? 8 : 4;
-    p.box_bytes = round_up((size_t)g.box * p.esz, 256);
+    p.fesz = storage == FDTD_F64 ? 8 : storage == FDTD_F32 ? 4 : 2;
+    p.cesz = storage == FDTD_F64 ? 8 : 4;  // 16-bit fields keep FP32 coefficients
+    p.fbox_bytes = round_up((size_t)g.box * p.fesz, 256);
+    p.cbox_bytes = round_up((size_t)g.box * p.cesz, 256);
     size_t off = 0;
     for (int b = 0; b < 2; ++b)
         for (int f = 0; f < 6; ++f) {
             p.off_fields[b][f] = off;
-            off += p.box_bytes;
+            off += p.fbox_bytes;
         }
     for (int f = 0; f < 3; ++f) {
         p.off_ce[f] = ce_arr ? off : SIZE_MAX;
-        if (ce_arr) off += p.box_bytes;
+        if (ce_arr) off += p.cbox_bytes;
     }
     for (int f = 0; f < 3; ++f) {
         p.off_ch[f] = ch_arr ? off : SIZE_MAX;
-        if (ch_arr) off += p.box_bytes;
+        if (ch_arr) off += p.cbox_bytes;
     }
     p.staging_bytes = round_up((size_t)(nx + 1) * (ny + 1) * (nz + 1) * sizeof(double), 256);
     p.off_staging = off;
@@ -176,18 +178,34 @@ Fields<T> fields_of(fdtd_t h, int b)
     return f;
 }
 
+// Coefficients in the compute type of storage T (FP32 for 16-bit fields).
 template <typename T>
-Coefs<T> coefs_of(fdtd_t h)
+Coefs<typename fdtd::Store<T>::C> coefs_of(fdtd_t h)
 {
-    Coefs<T> c;
+    using C = typename fdtd::Store<T>::C;
+    Coefs<C> c;
     for (int q = 0; q < 3; ++q) {
-        c.ce[q] = (const T *)h->ce[q];
-        c.ch[q] = (const T *)h->ch[q];
+        c.ce[q] = (const C *)h->ce[q];
+        c.ch[q] = (const C *)h->ch[q];
     }
-    c.ce_s = (T)h->ce_s;
-    c.ch_s = (T)h->ch_s;
+    c.ce_s = (C)h->ce_s;
+    c.ch_s = (C)h->ch_s;
     return c;
 }
+
+// Call fn with a value of the storage element type.
+template <typename Fn>
+auto by_storage(int storage, Fn &&fn)
+{
+    switch (storage) {
+    case FDTD_F64: return fn(double{});
+    case FDTD_F16: return fn(fdtd::f16{});
+    case FDTD_BF16: return fn(fdtd::bf16{});
+    default: return fn(float{});
+    }
+}
+
+bool is16(int storage) { return storage == FDTD_F16 || storage == FDTD_BF16; }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -211,7 +229,7 @@ int scan_material(const double *m, size_t n, double *mn, const char *name)
 int resolve_kernel(int kernel, int storage)
 {
     if (kernel == FDTD_KERNEL_AUTO)
-        return storage == FDTD_F32 ? FDTD_KERNEL_TEMPORAL : FDTD_KERNEL_SLAB;
+        return storage == FDTD_F64 ? FDTD_KERNEL_SLAB : FDTD_KERNEL_TEMPORAL;
     return kernel;
 }
 
@@ -226,19 +244,26 @@ int env_int(const char *name, int dflt)
 template <typename T>
 hipError_t launch_one(fdtd_t h, int kernel, int ts)
 {
-    const Coefs<T> c = coefs_of<T>(h);
-    if (kernel == FDTD_KERNEL_PLAIN)
-        return fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
+    const auto c = coefs_of<T>(h);
     hipError_t e;
-    if (kernel == FDTD_KERNEL_SLAB)
-        e = fdtd::launch_slab_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c, h->zchunk,
-                                      h->variant, h->stream);
-    else if (kernel == FDTD_KERNEL_TEMPORAL)
+    if constexpr (sizeof(T) == 2) {
+        // 16-bit storage is built for the temporal sweep only (ts = 1 for single steps)
+        (void)kernel;
         e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
                                           h->tzchunk, ts, h->tvariant, h->stream);
-    else
-        e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c, h->zchunk,
-                                       h->stream);
+    } else {
+        if (kernel == FDTD_KERNEL_PLAIN)
+            return fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
+        if (kernel == FDTD_KERNEL_SLAB)
+            e = fdtd::launch_slab_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
+                                          h->zchunk, h->variant, h->stream);
+        else if (kernel == FDTD_KERNEL_TEMPORAL)
+            e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
+                                              h->tzchunk, ts, h->tvariant, h->stream);
+        else
+            e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
+                                           h->zchunk, h->stream);
+    }
     h->cur = 1 - h->cur;
     return e;
 }
@@ -260,6 +285,7 @@ int step_impl(fdtd_t h, long long n)
         h->steps += h->tb;
         h->sweeps += 1;
     }
+    // single steps: the slab sweep (the temporal sweep with ts = 1 for 16-bit storage)
     const int single_kernel = h->kernel == FDTD_KERNEL_TEMPORAL ? FDTD_KERNEL_SLAB : h->kernel;
     for (long long s = 0; s < singles; ++s) {
         hipError_t e = launch_one<T>(h, single_kernel, 1);
@@ -335,12 +361,10 @@ int set_fields_common(fdtd_t h, const void *const src[6], int dtype, bool staged
         return fail(FDTD_E_ARG, "unsupported buffer dtype %d", dtype);
     if ((st = use_device(h)))
         return st;
-    hipError_t e;
-    const bool f32 = h->storage == FDTD_F32;
-    if (dtype == FDTD_F32)
-        e = f32 ? pack_all<float, float>(h, src, staged) : pack_all<float, double>(h, src, staged);
-    else
-        e = f32 ? pack_all<double, float>(h, src, staged) : pack_all<double, double>(h, src, staged);
+    hipError_t e = by_storage(h->storage, [&](auto tag) {
+        using T = decltype(tag);
+        return dtype == FDTD_F32 ? pack_all<float, T>(h, src, staged) : pack_all<double, T>(h, src, staged);
+    });
     if (e == hipSuccess && staged)
         e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess)
@@ -351,7 +375,7 @@ int set_fields_common(fdtd_t h, const void *const src[6], int dtype, bool staged
     return FDTD_OK;
 }
 
-int get_common(fdtd_t h, void *const dst[6], int dtype, bool staged, void *const *boxes)
+int get_common(fdtd_t h, void *const dst[6], int dtype, bool staged, void *const *boxes, bool coefs = false)
 {
     int st = check(h);
     if (st)
@@ -365,13 +389,13 @@ int get_common(fdtd_t h, void *const dst[6], int dtype, bool staged, void *const
         return fail(FDTD_E_ARG, "unsupported buffer dtype %d", dtype);
     if ((st = use_device(h)))
         return st;
-    hipError_t e;
-    const bool f32 = h->storage == FDTD_F32;
-    if (dtype == FDTD_F32)
-        e = f32 ? unpack_all<float, float>(h, dst, staged, boxes) : unpack_all<double, float>(h, dst, staged, boxes);
-    else
-        e = f32 ? unpack_all<float, double>(h, dst, staged, boxes)
-                : unpack_all<double, double>(h, dst, staged, boxes);
+    // coefficient boxes hold the compute type (FP32 for 16-bit fields)
+    const int st_box = coefs ? (h->storage == FDTD_F64 ? FDTD_F64 : FDTD_F32) : h->storage;
+    hipError_t e = by_storage(st_box, [&](auto tag) {
+        using T = decltype(tag);
+        return dtype == FDTD_F32 ? unpack_all<T, float>(h, dst, staged, boxes)
+                                 : unpack_all<T, double>(h, dst, staged, boxes);
+    });
     if (e != hipSuccess)
         return device_fail(h, e, "get_fields");
     return FDTD_OK;
@@ -400,7 +424,7 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
     fdtd_opts d;
     fdtd_opts_default(&d);
     const fdtd_opts *o = opts ? opts : &d;
-    if (o->storage != FDTD_F32 && o->storage != FDTD_F64)
+    if (o->storage < FDTD_F64 || o->storage > FDTD_BF16)
         return fail(FDTD_E_UNSUPPORTED, "storage dtype %d not built", o->storage);
     Plan p = make_plan(nx, ny, nz, o->storage, coef && coef->eps_r, coef && coef->mu_r);
     *out = p.total + 256;  // room to align an arbitrary arena base
@@ -421,13 +445,15 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     fdtd_opts d;
     fdtd_opts_default(&d);
     const fdtd_opts *o = opts ? opts : &d;
-    if (o->storage != FDTD_F32 && o->storage != FDTD_F64)
+    if (o->storage < FDTD_F64 || o->storage > FDTD_BF16)
         return fail(FDTD_E_UNSUPPORTED, "storage dtype %d not built", o->storage);
     if (o->kernel < FDTD_KERNEL_AUTO || o->kernel > FDTD_KERNEL_TEMPORAL)
         return fail(FDTD_E_ARG, "unknown kernel %d", o->kernel);
     int kern = resolve_kernel(o->kernel, o->storage);
-    if (kern == FDTD_KERNEL_TEMPORAL && o->storage != FDTD_F32)
-        return fail(FDTD_E_UNSUPPORTED, "the temporal kernel is built for FP32 storage only");
+    if (kern == FDTD_KERNEL_TEMPORAL && o->storage == FDTD_F64)
+        return fail(FDTD_E_UNSUPPORTED, "the temporal kernel is not built for FP64 storage");
+    if (is16(o->storage) && kern != FDTD_KERNEL_TEMPORAL)
+        return fail(FDTD_E_UNSUPPORTED, "16-bit storage is built for the temporal kernel only");
     if (kern == FDTD_KERNEL_TEMPORAL && (o->tb_steps < 0 || o->tb_steps > 3))
         return fail(FDTD_E_ARG, "tb_steps must be 1..3 (0: default 3), got %d", o->tb_steps);
     if (o->arena && o->arena_bytes == 0)
@@ -539,12 +565,12 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         h->own_arena = true;
     }
     base = (char *)round_up((uintptr_t)h->arena, 256);
-    const size_t guard = (size_t)fdtd::kGuardElems * p.esz;
+    const size_t fguard = (size_t)fdtd::kGuardElems * p.fesz, cguard = (size_t)fdtd::kGuardElems * p.cesz;
     for (int b = 0; b < 2; ++b)
-        for (int f = 0; f < 6; ++f) h->fld[b][f] = base + p.off_fields[b][f] + guard;
+        for (int f = 0; f < 6; ++f) h->fld[b][f] = base + p.off_fields[b][f] + fguard;
     for (int f = 0; f < 3; ++f) {
-        h->ce[f] = h->ce_arr ? base + p.off_ce[f] + guard : nullptr;
-        h->ch[f] = h->ch_arr ? base + p.off_ch[f] + guard : nullptr;
+        h->ce[f] = h->ce_arr ? base + p.off_ce[f] + cguard : nullptr;
+        h->ch[f] = h->ch_arr ? base + p.off_ch[f] + cguard : nullptr;
     }
     h->staging = base + p.off_staging;
     h->diag = (double *)(base + p.off_diag);
@@ -558,7 +584,7 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         e = hipMemcpyAsync(h->staging, m, ncell * sizeof(double), hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess)
             break;
-        if (h->storage == FDTD_F32) {
+        if (h->storage != FDTD_F64) {
             float *ce[3] = {nullptr, nullptr, nullptr}, *ch[3] = {nullptr, nullptr, nullptr};
             for (int f = 0; f < 3; ++f) (which == 0 ? ce : ch)[f] = (float *)(which == 0 ? h->ce[f] : h->ch[f]);
             e = fdtd::launch_coef<float>(p.g, dx, dt, which == 0 ? (const double *)h->staging : nullptr,
@@ -611,7 +637,7 @@ int fdtd_step(fdtd_t h, long long n)
         return fail(FDTD_E_STATE, "fields were never set");
     if ((st = use_device(h)))
         return st;
-    return h->storage == FDTD_F32 ? step_impl<float>(h, n) : step_impl<double>(h, n);
+    return by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, n); });
 }
 
 int fdtd_get_fields(fdtd_t h, void *const host[6], int host_dtype)
@@ -647,7 +673,7 @@ int fdtd_get_coefs(fdtd_t h, void *const host[6], int host_dtype)
         boxes[f] = h->ce[f];
         boxes[f + 3] = h->ch[f];
     }
-    int st = get_common(h, host, host_dtype, true, boxes);
+    int st = get_common(h, host, host_dtype, true, boxes, true);
     if (st)
         return st;
     const int nx = h->nx, ny = h->ny, nz = h->nz;
@@ -657,7 +683,7 @@ int fdtd_get_coefs(fdtd_t h, void *const host[6], int host_dtype)
             continue;
         int X, Y, Z;
         fdtd::extents(h->plan.g, f, X, Y, Z);
-        const double sv = h->storage == FDTD_F32 ? (double)(float)(f < 3 ? h->ce_s : h->ch_s)
+        const double sv = h->storage != FDTD_F64 ? (double)(float)(f < 3 ? h->ce_s : h->ch_s)
                                                  : (f < 3 ? h->ce_s : h->ch_s);
         for (int k = 0; k < Z; ++k)
             for (int j = 0; j < Y; ++j)
@@ -711,13 +737,11 @@ int fdtd_diag(fdtd_t h, double out[FDTD_DIAG_N])
         return st;
     double *partial = h->diag;
     double *dev_out = h->diag + fdtd::diag_partial_doubles();
-    hipError_t e;
-    if (h->storage == FDTD_F32)
-        e = fdtd::launch_diag<float>(h->plan.g, fields_of<float>(h, h->cur), coefs_of<float>(h), partial, dev_out,
-                                     h->stream);
-    else
-        e = fdtd::launch_diag<double>(h->plan.g, fields_of<double>(h, h->cur), coefs_of<double>(h), partial,
-                                      dev_out, h->stream);
+    hipError_t e = by_storage(h->storage, [&](auto tag) {
+        using T = decltype(tag);
+        return fdtd::launch_diag<T>(h->plan.g, fields_of<T>(h, h->cur), coefs_of<T>(h), partial, dev_out,
+                                    h->stream);
+    });
     double tmp[8] = {0};
     if (e == hipSuccess)
         e = hipMemcpyAsync(tmp, dev_out, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream);

@@ -22,6 +22,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "storage.h"
+
 namespace fdtd {
 
 struct Geom {
@@ -71,10 +73,12 @@ hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T>
                             const Coefs<T> &c, int zchunk, int variant, hipStream_t s);
 
 // Temporal step: ts (1..3) leapfrog steps in one sweep; reads src, writes dst.
-// Built for FP32 storage only.
+// Built for FP32, FP16 and BF16 field storage (16-bit fields compute in FP32
+// with FP32 coefficients).
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
-                                const Coefs<T> &c, int zchunk, int ts, int variant, hipStream_t s);
+                                const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant,
+                                hipStream_t s);
 int temporal_own_rows(int ts, int variant);
 int temporal_width(int variant);
 
@@ -101,8 +105,8 @@ hipError_t launch_unpack(const Geom &g, int field, const T *src, S *dst, hipStre
 // Diagnostics (FP64). partial must hold diag_partial_doubles() doubles.
 size_t diag_partial_doubles();
 template <typename T>
-hipError_t launch_diag(const Geom &g, const Fields<T> &f, const Coefs<T> &c, double *partial,
-                       double *out_dev, hipStream_t s);
+hipError_t launch_diag(const Geom &g, const Fields<T> &f, const Coefs<typename Store<T>::C> &c,
+                       double *partial, double *out_dev, hipStream_t s);
 
 // Whether the tiled sweeps number their workgroups for the 8 XCDs (1, the
 // default) or in plain launch order (0); FDTD_XCD_REMAP=0 selects the latter.

@@ -9,6 +9,7 @@
 // A fixed grid of workgroups walks the nodes in a fixed order, so the sums
 // do not depend on scheduling.
 #include "fdtd_internal.h"
+#include "storage.h"
 
 namespace fdtd {
 namespace {
@@ -39,7 +40,14 @@ __device__ __forceinline__ double coef_at(const T *arr, T s, bool zero, long lon
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_diag(Geom g, Fields<T> f, Coefs<T> c, double *partial)
+__device__ __forceinline__ double val(const T *a, long long o)
+{
+    return (double)Store<T>::widen(a[o]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_diag(Geom g, Fields<T> f, Coefs<typename Store<T>::C> c, double *partial)
 {
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const long long X = nx + 1, Y = ny + 1, n = X * Y * (nz + 1);
@@ -59,7 +67,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geom g, Fields<T> f, Coefs<T> c
         }
         for (int q = 0; q < 3; ++q) {
             if (!ex[q]) continue;
-            double e = (double)f.f[q][o];
+            double e = val(f.f[q], o);
             if (!isfinite(e)) bad += 1;
             se += e * e;
             const bool wall = e_tan(q, i, j, k, nx, ny, nz);
@@ -70,11 +78,11 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geom g, Fields<T> f, Coefs<T> c
                 if (ce != 0.0) w += e * e / ce;
             }
         }
-        const double Ex0 = ex[0] ? (double)f.f[0][o] : 0.0, Ey0 = ex[1] ? (double)f.f[1][o] : 0.0,
-                     Ez0 = ex[2] ? (double)f.f[2][o] : 0.0;
+        const double Ex0 = ex[0] ? val(f.f[0], o) : 0.0, Ey0 = ex[1] ? val(f.f[1], o) : 0.0,
+                     Ez0 = ex[2] ? val(f.f[2], o) : 0.0;
         for (int q = 3; q < 6; ++q) {
             if (!ex[q]) continue;
-            double h = (double)f.f[q][o];
+            double h = val(f.f[q], o);
             if (!isfinite(h)) bad += 1;
             sh += h * h;
             if (h_normal(q, i, j, k, nx, ny, nz)) continue;
@@ -82,11 +90,11 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geom g, Fields<T> f, Coefs<T> c
             if (ch == 0.0) continue;
             double d;
             if (q == 3)
-                d = ((double)f.f[1][o + P] - Ey0) - ((double)f.f[2][o + px] - Ez0);
+                d = (val(f.f[1], o + P) - Ey0) - (val(f.f[2], o + px) - Ez0);
             else if (q == 4)
-                d = ((double)f.f[2][o + 1] - Ez0) - ((double)f.f[0][o + P] - Ex0);
+                d = (val(f.f[2], o + 1) - Ez0) - (val(f.f[0], o + P) - Ex0);
             else
-                d = ((double)f.f[0][o + px] - Ex0) - ((double)f.f[1][o + 1] - Ey0);
+                d = (val(f.f[0], o + px) - Ex0) - (val(f.f[1], o + 1) - Ey0);
             const double hn = h + ch * d;
             w += h * hn / ch;
         }
@@ -96,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) k_diag(Geom g, Fields<T> f, Coefs<T> c
                 if (h_normal(q, ii, jj, kk, nx, ny, nz)) return 0.0;
                 const long long oo = g.at(ii, jj, kk);
                 const double ch = coef_at(c.ch[q - 3], c.ch_s, false, oo);
-                return ch != 0.0 ? (double)f.f[q][oo] / ch : 0.0;
+                return ch != 0.0 ? val(f.f[q], oo) / ch : 0.0;
             };
             const double dv = (b(3, i + 1, j, k) - b(3, i, j, k)) + (b(4, i, j + 1, k) - b(4, i, j, k)) +
                               (b(5, i, j, k + 1) - b(5, i, j, k));
@@ -152,8 +160,8 @@ __global__ void __launch_bounds__(kBlock) k_diag_final(const double *partial, do
 size_t diag_partial_doubles() { return (size_t)kGrid * kQ; }
 
 template <typename T>
-hipError_t launch_diag(const Geom &g, const Fields<T> &f, const Coefs<T> &c, double *partial, double *out_dev,
-                       hipStream_t s)
+hipError_t launch_diag(const Geom &g, const Fields<T> &f, const Coefs<typename Store<T>::C> &c, double *partial,
+                       double *out_dev, hipStream_t s)
 {
     hipLaunchKernelGGL((k_diag<T>), dim3(kGrid), dim3(kBlock), 0, s, g, f, c, partial);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, s, partial, out_dev);
@@ -164,5 +172,9 @@ template hipError_t launch_diag<float>(const Geom &, const Fields<float> &, cons
                                        double *, hipStream_t);
 template hipError_t launch_diag<double>(const Geom &, const Fields<double> &, const Coefs<double> &, double *,
                                         double *, hipStream_t);
+template hipError_t launch_diag<f16>(const Geom &, const Fields<f16> &, const Coefs<float> &, double *, double *,
+                                     hipStream_t);
+template hipError_t launch_diag<bf16>(const Geom &, const Fields<bf16> &, const Coefs<float> &, double *, double *,
+                                      hipStream_t);
 
 }  // namespace fdtd

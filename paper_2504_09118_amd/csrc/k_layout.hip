@@ -7,6 +7,7 @@
 //           rounded once to the storage type (Eq. 2 coefficients dt/eps and
 //           dt/mu with the cubic-cell 1/dx folded in)
 #include "fdtd_internal.h"
+#include "storage.h"
 
 namespace fdtd {
 namespace {
@@ -40,9 +41,10 @@ __global__ void __launch_bounds__(kBlock) k_pack(Geom g, int field, int X, int Y
         return;
     int i, j, k;
     unflatten(l, X, Y, i, j, k);
-    T v = (T)src[l];
+    // 16-bit storage: the host value is rounded to FP32, then to the 16-bit type
+    T v = Store<T>::narrow((typename Store<T>::C)src[l]);
     if (e_wall(field, i, j, k, g.nx, g.ny, g.nz))
-        v = (T)0;
+        v = Store<T>::narrow(0);
     long long o = g.at(i, j, k);
     dst[o] = v;
     if (dst2)
@@ -58,7 +60,7 @@ __global__ void __launch_bounds__(kBlock) k_unpack(Geom g, int X, int Y, long lo
         return;
     int i, j, k;
     unflatten(l, X, Y, i, j, k);
-    dst[l] = (S)src[g.at(i, j, k)];
+    dst[l] = (S)Store<T>::widen(src[g.at(i, j, k)]);
 }
 
 __device__ __forceinline__ double mat(const double *m, int nx, int ny, int i, int j, int k)
@@ -166,6 +168,14 @@ template hipError_t launch_pack<double, float>(const Geom &, int, const double *
 template hipError_t launch_pack<float, double>(const Geom &, int, const float *, double *, double *, hipStream_t);
 template hipError_t launch_pack<double, double>(const Geom &, int, const double *, double *, double *,
                                                 hipStream_t);
+template hipError_t launch_pack<float, f16>(const Geom &, int, const float *, f16 *, f16 *, hipStream_t);
+template hipError_t launch_pack<double, f16>(const Geom &, int, const double *, f16 *, f16 *, hipStream_t);
+template hipError_t launch_pack<float, bf16>(const Geom &, int, const float *, bf16 *, bf16 *, hipStream_t);
+template hipError_t launch_pack<double, bf16>(const Geom &, int, const double *, bf16 *, bf16 *, hipStream_t);
+template hipError_t launch_unpack<f16, float>(const Geom &, int, const f16 *, float *, hipStream_t);
+template hipError_t launch_unpack<f16, double>(const Geom &, int, const f16 *, double *, hipStream_t);
+template hipError_t launch_unpack<bf16, float>(const Geom &, int, const bf16 *, float *, hipStream_t);
+template hipError_t launch_unpack<bf16, double>(const Geom &, int, const bf16 *, double *, hipStream_t);
 template hipError_t launch_unpack<float, float>(const Geom &, int, const float *, float *, hipStream_t);
 template hipError_t launch_unpack<float, double>(const Geom &, int, const float *, double *, hipStream_t);
 template hipError_t launch_unpack<double, float>(const Geom &, int, const double *, float *, hipStream_t);

@@ -29,6 +29,7 @@
 // curl_update with the operand order of every other schedule: TS sweeps of
 // this kernel equal TS single steps bit for bit.
 #include "fdtd_internal.h"
+#include "storage.h"
 #include "yee_update.h"
 
 namespace fdtd {
@@ -57,16 +58,52 @@ __device__ __forceinline__ typename V2<T>::type ld2(const T *plane, unsigned bof
     return *(FDTD_GLOBAL const typename V2<T>::type *)(uni(plane) + boff);
 }
 
-template <typename T>
-__device__ __forceinline__ void st2(T *plane, unsigned boff, const typename V2<T>::type &x)
+// Two consecutive field cells of storage type S, widened to the compute type.
+template <typename S>
+__device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *plane, unsigned boff)
 {
-    *(FDTD_GLOBAL typename V2<T>::type *)(uni(plane) + boff) = x;
+    using C = typename Store<S>::C;
+    if constexpr (sizeof(S) == 2) {
+        const unsigned u = *(FDTD_GLOBAL const unsigned *)(uni(plane) + boff);
+        const unsigned short ua = (unsigned short)(u & 0xffffu), ub = (unsigned short)(u >> 16);
+        S a, b;
+        __builtin_memcpy(&a, &ua, 2);
+        __builtin_memcpy(&b, &ub, 2);
+        typename V2<C>::type r;
+        r[0] = Store<S>::widen(a);
+        r[1] = Store<S>::widen(b);
+        return r;
+    } else {
+        return *(FDTD_GLOBAL const typename V2<C>::type *)(uni(plane) + boff);
+    }
 }
 
-template <typename T>
-__device__ __forceinline__ void st1(T *plane, unsigned boff, T x)
+// Round two compute-type cells to the storage type (nearest even) and store them.
+template <typename S>
+__device__ __forceinline__ void stf(S *plane, unsigned boff, const typename V2<typename Store<S>::C>::type &x)
 {
-    *(FDTD_GLOBAL T *)(uni(plane) + boff) = x;
+    if constexpr (sizeof(S) == 2) {
+        const S a = Store<S>::narrow(x[0]), b = Store<S>::narrow(x[1]);
+        unsigned short ua, ub;
+        __builtin_memcpy(&ua, &a, 2);
+        __builtin_memcpy(&ub, &b, 2);
+        *(FDTD_GLOBAL unsigned *)(uni(plane) + boff) = (unsigned)ua | ((unsigned)ub << 16);
+    } else {
+        *(FDTD_GLOBAL typename V2<typename Store<S>::C>::type *)(uni(plane) + boff) = x;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void stf1(S *plane, unsigned boff, typename Store<S>::C x)
+{
+    if constexpr (sizeof(S) == 2) {
+        const S a = Store<S>::narrow(x);
+        unsigned short ua;
+        __builtin_memcpy(&ua, &a, 2);
+        *(FDTD_GLOBAL unsigned short *)(uni(plane) + boff) = ua;
+    } else {
+        *(FDTD_GLOBAL S *)(uni(plane) + boff) = x;
+    }
 }
 
 // Workgroup shape of the temporal sweep: 16 waves; RPW rows per wave
@@ -85,13 +122,14 @@ struct TShape {
     static_assert(2 * NVH * R <= 64 * NHW, "halo lanes do not fit");
 };
 
-template <typename T, int TS, int RPW, bool CE_ARR, bool CH_ARR>
+template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR>
 __global__ void __launch_bounds__(1024)
-    k_temporal(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles,
-               int xcd_remap)
+    k_temporal(Geom g, Fields<S> src, Fields<S> dst, Coefs<typename Store<S>::C> c, int kchunk, int ntx, int nty,
+               int ntiles, int xcd_remap)
 {
-    using S = TShape<TS, RPW>;
-    constexpr int V = S::V, W = S::W, NVH = S::NVH, HX = S::HX, R = S::R, NRW = S::NRW, LPR = S::LPR;
+    using T = typename Store<S>::C;  // compute type (FP32 for 16-bit storage)
+    using Sh = TShape<TS, RPW>;
+    constexpr int V = Sh::V, W = Sh::W, NVH = Sh::NVH, HX = Sh::HX, R = Sh::R, NRW = Sh::NRW, LPR = Sh::LPR;
     constexpr int LP = HX + W + HX + V;     // LDS row pitch (one pad vector at the end)
     constexpr int RB = R + 2;               // LDS rows (one pad row each side)
     using vec = typename V2<T>::type;
@@ -147,12 +185,13 @@ __global__ void __launch_bounds__(1024)
     const bool act = lane_ok && j >= 0 && j < ny && ib >= 0 && ib < nx;
     const bool own = main_wave && row >= TS && row < R - TS && act;
     const bool full = ib + V <= nx;
-    const unsigned off = (unsigned)(ib + px * j) * (unsigned)sizeof(T);
+    const unsigned offs = (unsigned)(ib + px * j) * (unsigned)sizeof(S);  // field byte offset in a plane
+    const unsigned offc = (unsigned)(ib + px * j) * (unsigned)sizeof(T);  // coefficient byte offset
     const int lr = row + 1;     // LDS row
     const int lc = HX + c0;     // LDS column of the first cell
 
-    const T *Ex = src.f[0], *Ey = src.f[1], *Ez = src.f[2];
-    const T *Hx = src.f[3], *Hy = src.f[4], *Hz = src.f[5];
+    const S *Ex = src.f[0], *Ey = src.f[1], *Ez = src.f[2];
+    const S *Hx = src.f[3], *Hy = src.f[4], *Hz = src.f[5];
     const vec zero = (vec)(T)0;
 
     // per-stage registers (index s-1)
@@ -180,26 +219,26 @@ __global__ void __launch_bounds__(1024)
     // first planes of stage 1
     if (act) {
         const long long pk = (long long)k0 * P;
-        Ecur[0][0] = ld2(Ex + pk, off);
-        Ecur[0][1] = ld2(Ey + pk, off);
-        Ecur[0][2] = ld2(Ez + pk, off);
+        Ecur[0][0] = ldf(Ex + pk, offs);
+        Ecur[0][1] = ldf(Ey + pk, offs);
+        Ecur[0][2] = ldf(Ez + pk, offs);
         if (k0 + 1 < nz) {
-            En1[0] = ld2(Ex + pk + P, off);
-            En1[1] = ld2(Ey + pk + P, off);
-            En1[2] = ld2(Ez + pk + P, off);
+            En1[0] = ldf(Ex + pk + P, offs);
+            En1[1] = ldf(Ey + pk + P, offs);
+            En1[2] = ldf(Ez + pk + P, offs);
         }
-        Hold[0][0] = ld2(Hx + pk, off);
-        Hold[0][1] = ld2(Hy + pk, off);
-        Hold[0][2] = ld2(Hz + pk, off);
+        Hold[0][0] = ldf(Hx + pk, offs);
+        Hold[0][1] = ldf(Hy + pk, offs);
+        Hold[0][2] = ldf(Hz + pk, offs);
         if (CE_ARR) {
-            Ce[0][0] = ld2(c.ce[0] + pk, off);
-            Ce[0][1] = ld2(c.ce[1] + pk, off);
-            Ce[0][2] = ld2(c.ce[2] + pk, off);
+            Ce[0][0] = ld2(c.ce[0] + pk, offc);
+            Ce[0][1] = ld2(c.ce[1] + pk, offc);
+            Ce[0][2] = ld2(c.ce[2] + pk, offc);
         }
         if (CH_ARR) {
-            Ch[0][0] = ld2(c.ch[0] + pk, off);
-            Ch[0][1] = ld2(c.ch[1] + pk, off);
-            Ch[0][2] = ld2(c.ch[2] + pk, off);
+            Ch[0][0] = ld2(c.ch[0] + pk, offc);
+            Ch[0][1] = ld2(c.ch[1] + pk, offc);
+            Ch[0][2] = ld2(c.ch[2] + pk, offc);
         }
     }
     __syncthreads();  // LDS zeroing done
@@ -211,22 +250,22 @@ __global__ void __launch_bounds__(1024)
         if (act && k + 1 <= kend && k + 1 < nz) {
             const long long pk1 = (long long)(k + 1) * P;
             if (k + 2 < nz) {
-                pE[0] = ld2(Ex + pk1 + P, off);
-                pE[1] = ld2(Ey + pk1 + P, off);
-                pE[2] = ld2(Ez + pk1 + P, off);
+                pE[0] = ldf(Ex + pk1 + P, offs);
+                pE[1] = ldf(Ey + pk1 + P, offs);
+                pE[2] = ldf(Ez + pk1 + P, offs);
             }
-            pH[0] = ld2(Hx + pk1, off);
-            pH[1] = ld2(Hy + pk1, off);
-            pH[2] = ld2(Hz + pk1, off);
+            pH[0] = ldf(Hx + pk1, offs);
+            pH[1] = ldf(Hy + pk1, offs);
+            pH[2] = ldf(Hz + pk1, offs);
             if (CE_ARR) {
-                pCe[0] = ld2(c.ce[0] + pk1, off);
-                pCe[1] = ld2(c.ce[1] + pk1, off);
-                pCe[2] = ld2(c.ce[2] + pk1, off);
+                pCe[0] = ld2(c.ce[0] + pk1, offc);
+                pCe[1] = ld2(c.ce[1] + pk1, offc);
+                pCe[2] = ld2(c.ce[2] + pk1, offc);
             }
             if (CH_ARR) {
-                pCh[0] = ld2(c.ch[0] + pk1, off);
-                pCh[1] = ld2(c.ch[1] + pk1, off);
-                pCh[2] = ld2(c.ch[2] + pk1, off);
+                pCh[0] = ld2(c.ch[0] + pk1, offc);
+                pCh[1] = ld2(c.ch[1] + pk1, offc);
+                pCh[2] = ld2(c.ch[2] + pk1, offc);
             }
         }
         // ---------------- stage the E input of every stage ----------------
@@ -355,20 +394,20 @@ __global__ void __launch_bounds__(1024)
                 if (own && pp >= kb) {
                     const long long pk = (long long)pp * P;
                     if (full) {
-                        st2(dst.f[0] + pk, off, ex);
-                        st2(dst.f[1] + pk, off, ey);
-                        st2(dst.f[2] + pk, off, ez);
-                        st2(dst.f[3] + pk, off, hout[sp][0]);
-                        st2(dst.f[4] + pk, off, hout[sp][1]);
-                        st2(dst.f[5] + pk, off, hout[sp][2]);
+                        stf(dst.f[0] + pk, offs, ex);
+                        stf(dst.f[1] + pk, offs, ey);
+                        stf(dst.f[2] + pk, offs, ez);
+                        stf(dst.f[3] + pk, offs, hout[sp][0]);
+                        stf(dst.f[4] + pk, offs, hout[sp][1]);
+                        stf(dst.f[5] + pk, offs, hout[sp][2]);
                     } else {
                         // V = 2: only the first cell is in the domain
-                        st1(dst.f[0] + pk, off, ex[0]);
-                        st1(dst.f[1] + pk, off, ey[0]);
-                        st1(dst.f[2] + pk, off, ez[0]);
-                        st1(dst.f[3] + pk, off, hout[sp][0][0]);
-                        st1(dst.f[4] + pk, off, hout[sp][1][0]);
-                        st1(dst.f[5] + pk, off, hout[sp][2][0]);
+                        stf1(dst.f[0] + pk, offs, ex[0]);
+                        stf1(dst.f[1] + pk, offs, ey[0]);
+                        stf1(dst.f[2] + pk, offs, ez[0]);
+                        stf1(dst.f[3] + pk, offs, hout[sp][0][0]);
+                        stf1(dst.f[4] + pk, offs, hout[sp][1][0]);
+                        stf1(dst.f[5] + pk, offs, hout[sp][2][0]);
                     }
                 }
             }
@@ -407,14 +446,14 @@ __global__ void __launch_bounds__(1024)
 }
 
 template <typename T, int TS, int RPW>
-hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c, int zchunk,
-                     hipStream_t s)
+hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
+                     const Coefs<typename Store<T>::C> &c, int zchunk, hipStream_t s)
 {
-    using S = TShape<TS, RPW>;
+    using Sh = TShape<TS, RPW>;
     const int kchunk = (g.nz + zchunk - 1) / zchunk;
     const int nzc = (g.nz + kchunk - 1) / kchunk;
-    const int own = S::R - 2 * TS;
-    const int ntx = (g.nx + S::W - 1) / S::W, nty = (g.ny + own - 1) / own;
+    const int own = Sh::R - 2 * TS;
+    const int ntx = (g.nx + Sh::W - 1) / Sh::W, nty = (g.ny + own - 1) / own;
     const int ntiles = ntx * nty * nzc;
     const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
     dim3 block(64, 16), grid(nblocks);
@@ -445,8 +484,9 @@ int temporal_own_rows(int ts, int variant)
 int temporal_width(int variant) { return variant == 1 ? 128 : 64; }
 
 template <typename T>
-hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c,
-                                int zchunk, int ts, int variant, hipStream_t s)
+hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
+                                const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant,
+                                hipStream_t s)
 {
     zchunk = zchunk < 1 ? 1 : zchunk;
     if (variant == 1) {
@@ -467,6 +507,10 @@ hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Field
 
 template hipError_t launch_temporal_step<float>(const Geom &, const Fields<float> &, const Fields<float> &,
                                                 const Coefs<float> &, int, int, int, hipStream_t);
+template hipError_t launch_temporal_step<f16>(const Geom &, const Fields<f16> &, const Fields<f16> &,
+                                              const Coefs<float> &, int, int, int, hipStream_t);
+template hipError_t launch_temporal_step<bf16>(const Geom &, const Fields<bf16> &, const Fields<bf16> &,
+                                               const Coefs<float> &, int, int, int, hipStream_t);
 
 }  // namespace fdtd
 

@@ -16,7 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
 OK, E_ARG, E_CFL, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-F64, F32 = 0, 1
+F64, F32, F16, BF16 = 0, 1, 2, 3
+STORAGE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+STORAGE_NAMES = {v: k for k, v in STORAGE.items()}
 KERNELS = {"auto": 0, "plain": 1, "fused": 2, "slab": 3, "temporal": 4}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 DIAG_NAMES = ("energy", "sum_e2", "sum_h2", "max_div_b", "max_e_tan", "nonfinite")
@@ -124,7 +126,7 @@ def required_bytes(nx, ny, nz, eps_r=None, mu_r=None, storage="f32", kernel="aut
     coef = _Coef(eps_r=1 if eps_r is not None else None, mu_r=1 if mu_r is not None else None)
     opts = _Opts()
     lib.fdtd_opts_default(ctypes.byref(opts))
-    opts.storage = F32 if storage == "f32" else F64
+    opts.storage = STORAGE[storage]
     opts.kernel = KERNELS[kernel]
     out = ctypes.c_size_t(0)
     _check(lib.fdtd_required_bytes(nx, ny, nz, ctypes.byref(coef), ctypes.byref(opts), ctypes.byref(out)))
@@ -134,7 +136,8 @@ def required_bytes(nx, ny, nz, eps_r=None, mu_r=None, storage="f32", kernel="aut
 class Solver:
     """One PEC-cavity Yee solver living on one GPU.
 
-    storage: "f32" (default) or "f64" (test-only double-precision fields).
+    storage: "f32" (default), "f64" (test-only double-precision fields), or
+    "f16" / "bf16" (16-bit fields computed in FP32, rounded once per sweep).
     kernel: "auto", "plain", "fused", "slab" or "temporal"; tb_steps: steps
     per sweep for "temporal".
     stream: a hipStream_t handle (int), a torch.cuda.Stream, or "torch" for
@@ -157,9 +160,9 @@ class Solver:
                      mu_r=mu.ctypes.data if mu is not None else None)
         opts = _Opts()
         self._lib.fdtd_opts_default(ctypes.byref(opts))
-        if storage not in ("f32", "f64"):
+        if storage not in STORAGE:
             raise ValueError(f"unsupported storage {storage!r}")
-        opts.storage = F32 if storage == "f32" else F64
+        opts.storage = STORAGE[storage]
         opts.kernel = KERNELS[kernel]
         opts.tb_steps = int(tb_steps)
         opts.device = int(device)
@@ -257,7 +260,7 @@ class Solver:
         out = (ctypes.c_longlong * 8)()
         _check(self._lib.fdtd_query(self._h, out))
         return {"kernel": KERNEL_NAMES.get(out[0], out[0]), "steps_per_sweep": out[1],
-                "storage": "f32" if out[2] == F32 else "f64", "sweeps": out[3], "ce_array": bool(out[4]),
+                "storage": STORAGE_NAMES.get(out[2], out[2]), "sweeps": out[3], "ce_array": bool(out[4]),
                 "ch_array": bool(out[5]), "pitch_x": out[6], "device_bytes": out[7]}
 
     @property

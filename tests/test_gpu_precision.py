@@ -1,0 +1,122 @@
+"""16-bit field storage (FP16, BF16) with FP32 compute, against the FP64 oracle.
+
+Two references, both computed by the oracle from the same rounded inputs:
+- exact: the FP64 oracle (parity mode, FP32-rounded coefficients) with no
+  storage rounding; the distance to it is the storage error, reported per
+  configuration with a stated bound;
+- emulated: the FP64 oracle with the state rounded to the 16-bit type after
+  every sweep (every tb steps), i.e. the storage rule of the GPU path with
+  exact arithmetic in between; the GPU result must sit much closer to it.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import cavity_inputs as ci
+import oracle
+from tests.test_gpu_parity import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+S = 0.5 / math.sqrt(3.0)
+
+
+def round_bf16(a):
+    """Round FP64 values to bfloat16 via FP32 (nearest even), returned as FP64."""
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    nan = np.isnan(f)
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out
+
+
+def round_store(a, storage):
+    if storage == "f16":
+        return np.asarray(a, dtype=np.float32).astype(np.float16).astype(np.float64)
+    if storage == "bf16":
+        return round_bf16(a)
+    raise ValueError(storage)
+
+
+def oracle_runs(nx, ny, nz, e32, eps, steps, tb, storage):
+    ce = oracle.round_to(oracle.coef_e(nx, ny, nz, 1.0, S, eps), np.float32)
+    ch = oracle.round_to(oracle.coef_h(nx, ny, nz, 1.0, S), np.float32)
+    e16 = [round_store(a, storage) for a in e32]
+    exact = oracle.make_state(e16)
+    oracle.run(exact, ce, ch, steps)
+    emu = oracle.make_state(e16)
+    done = 0
+    while done < steps:
+        n = min(tb, steps - done)
+        oracle.run(emu, ce, ch, n)
+        for a in emu:
+            a[...] = round_store(a, storage)
+        done += n
+    return exact, emu
+
+
+CASES = [
+    # (dims, steps, tb, storage, bound vs exact FP64 oracle)
+    ((32, 32, 32), 100, 3, "f16", 2e-3),
+    ((32, 32, 32), 100, 3, "bf16", 2e-2),
+    ((40, 36, 44), 1000, 3, "f16", 6e-3),
+    ((40, 36, 44), 1000, 3, "bf16", 5e-2),
+    ((40, 36, 44), 300, 2, "f16", 4e-3),
+]
+
+
+@pytest.mark.parametrize("dims,steps,tb,storage,bound", CASES)
+def test_16bit_storage_error(dims, steps, tb, storage, bound):
+    from paper_2504_09118_amd import Solver
+
+    nx, ny, nz = dims
+    eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=6)
+    e32 = ci.random_e(nx, ny, nz, seed=1, dtype=np.float32)
+    with Solver(nx, ny, nz, 1.0, S, eps_r=eps, storage=storage, kernel="temporal", tb_steps=tb) as s:
+        s.set_fields(e32)
+        s.step(steps)
+        got = s.get_fields()
+        d = s.diag()
+    exact, emu = oracle_runs(nx, ny, nz, e32, eps, steps, tb, storage)
+    err_exact = rel_l2(got, exact)
+    err_emu = rel_l2(got, emu)
+    print(f"\n{storage} {dims} {steps} steps tb={tb}: rel-L2 vs FP64 oracle {err_exact:.3e}, "
+          f"vs emulated {storage} storage {err_emu:.3e}")
+    assert err_exact < bound
+    assert err_emu < 0.25 * err_exact
+    assert oracle.tangential_max(got) == 0.0
+    assert d["nonfinite"] == 0
+
+
+def test_16bit_storage_is_deterministic():
+    from paper_2504_09118_amd import Solver
+
+    nx, ny, nz = 70, 19, 37
+    e32 = ci.random_e(nx, ny, nz, seed=5, dtype=np.float32)
+    outs = []
+    for _ in range(2):
+        with Solver(nx, ny, nz, 1.0, S, storage="f16", tb_steps=3) as s:
+            s.set_fields(e32)
+            s.step(50)
+            outs.append(s.get_fields(np.float32))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_bf16_rounding_matches_reference():
+    """The device's float -> bfloat16 rounding equals round_bf16 (set, then get)."""
+    from paper_2504_09118_amd import Solver
+
+    nx, ny, nz = 9, 7, 5
+    h = ci.random_h(nx, ny, nz, seed=3, dtype=np.float32)
+    e = ci.random_e(nx, ny, nz, seed=3, dtype=np.float32)
+    with Solver(nx, ny, nz, 1.0, S, storage="bf16") as s:
+        s.set_fields(e, h)
+        got = s.get_fields()
+    for g, a in zip(got[3:], h):
+        assert np.array_equal(g, round_bf16(a))
