@@ -25,6 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+STORAGE_LABEL = {"f32": "FP32", "f16": "FP16", "bf16": "BF16"}
 
 
 def algorithmic_bytes_per_cell_step(kernel: str, ce_arrays: bool, ch_arrays: bool, field_bytes: int = 4,
@@ -145,7 +146,7 @@ def main() -> int:
         traffic, traffic_src = recorded_traffic(kernel, steps_per_launch, nx)
 
     result = {
-        "metric": f"Gcell-updates/s ({nx}^3 {args.storage.upper()} PEC cavity, spherical eps inclusions)",
+        "metric": f"Gcell-updates/s ({nx}^3 {STORAGE_LABEL[args.storage]} PEC cavity, spherical eps inclusions)",
         "value": round(gcells, 3),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
@@ -155,11 +156,12 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage == "f32" else f"{args.storage} storage, f32 compute",
+        "dtype": "f32",
         "data": "synthetic: 32 seeded spherical inclusions eps_r~U[1,4], E~U[-1,1] (SplitMix64), H=0",
-        "config": {"workload": f"box cavity {nx}x{ny}x{nz}, {args.storage.upper()} fields, per-node Ce from per-cell eps_r, "
+        "config": {"workload": f"box cavity {nx}x{ny}x{nz}, {STORAGE_LABEL[args.storage]} fields, per-node Ce from per-cell eps_r, "
                                f"scalar Ch, Courant 0.5/sqrt(3)",
-                   "kernel": kernel, "steps_per_launch": steps_per_launch, "parallelism": "single GPU"},
+                   "kernel": kernel, "steps_per_launch": steps_per_launch, "field_storage": args.storage,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_source": traffic_src,
