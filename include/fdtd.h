@@ -55,7 +55,8 @@ typedef enum {
     FDTD_E_NOMEM = -3,        /* device memory or the caller's arena is too small */
     FDTD_E_DEVICE = -4,       /* a HIP call or a kernel failed */
     FDTD_E_STATE = -5,        /* NULL / destroyed / errored handle, or fields never set */
-    FDTD_E_UNSUPPORTED = -6   /* option combination not built */
+    FDTD_E_UNSUPPORTED = -6,  /* option combination not built */
+    FDTD_E_TIMEOUT = -7       /* a pool wait ran out of time (nothing failed) */
 } fdtd_status;
 
 /*
@@ -141,6 +142,19 @@ int fdtd_set_fields(fdtd_t h, const void *const host[6], int host_dtype);
 int fdtd_set_fields_device(fdtd_t h, const void *const dev[6], int dev_dtype);
 
 /*
+ * Set the state to a seeded random (E^0, H^{-1/2}) on the device, the random
+ * initial state of the cavity workloads (Fig. 1b, Sec. 4): every E node not
+ * tangential to a wall takes 2u - 1 with u = (SplitMix64 output >> 11) 2^-53,
+ * computed in FP64 and rounded once to the storage type (16-bit storage:
+ * FP64 -> FP32 -> 16-bit). SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) is
+ * used counter-style: output c of seed s is mix64(s + (c+1)*0x9E3779B97F4A7C15
+ * mod 2^64), and component f (0 Ex, 1 Ey, 2 Ez) at linear index l of the host
+ * layout uses counter (f << 40) + l. Tangential E on the walls and all H are
+ * 0. Resets the step counter. Enqueued on the solver's stream (no wait).
+ */
+int fdtd_init_random(fdtd_t h, unsigned long long seed);
+
+/*
  * Enqueue n >= 0 leapfrog steps (Sec. 2.1 algorithm listing: H update, H
  * boundary, E update, E boundary). Asynchronous: returns after launching.
  * Launch failures return FDTD_E_DEVICE at once; faults during execution
@@ -195,6 +209,123 @@ void *fdtd_stream(fdtd_t h);
 
 /* Release device memory the library allocated (not a caller arena) and the handle. */
 int fdtd_destroy(fdtd_t h);
+
+/*
+ * ---- Serving pool: continuous batching of many cavity solves ----
+ *
+ * A pool owns one block of device memory (hbm_budget bytes) and a host thread
+ * that runs the request loop. Submitted requests wait in a queue until their
+ * state fits the free memory (first fit; FIFO unless backfill is set, which
+ * lets a later request that fits pass one that does not). Admitted requests
+ * keep their fields resident; each loop round advances every admitted request
+ * by min(tb_steps, steps left) leapfrog steps (the Sec. 2.1 algorithm
+ * listing) in ONE temporal-sweep launch over the tiles of all of them (one
+ * launch per distinct (steps, per-node Ce, per-node Ch) group). A request
+ * leaves the batch after its last step; new requests join at the next round.
+ * Per-request arithmetic is the single-solve tile code on its own buffers, so
+ * a request gives the same bits alone and in any mix, and the same bits as an
+ * FP32 fdtd_t solver with the same dims, coefficients, initial state and
+ * steps. Storage is FP32.
+ *
+ * Timing: t_submit, t_admit, t_done are host steady-clock seconds since pool
+ * creation; t_done is when the loop thread observed the completion event
+ * recorded after the request's last sweep (it waits on launches in order, so
+ * the observation trails the device by at most one batched launch).
+ */
+typedef struct fdtd_pool *fdtd_pool_t;
+
+typedef struct {
+    size_t hbm_budget; /* device bytes for request state (>= 1 MiB); with arena: its size */
+    int device;        /* HIP device ordinal */
+    int tb_steps;      /* steps per batched sweep, 1..3 (0: 3) */
+    int max_active;    /* most admitted requests at once, 1..65536 (0: 256) */
+    int backfill;      /* 0: strict FIFO admission; 1: requests that fit may pass the queue head */
+    void *stream;      /* hipStream_t for all request work; NULL: the pool creates one */
+    void *arena;       /* caller-owned device memory of hbm_budget bytes; NULL: hipMalloc */
+} fdtd_pool_opts;
+
+typedef struct {
+    int nx, ny, nz;              /* cells, each >= 2 */
+    double dx, dt;               /* as fdtd_create (Courant limit checked) */
+    long long steps;             /* leapfrog steps, >= 0 */
+    const double *eps_r, *mu_r;  /* per-cell materials as fdtd_coef (NULL: 1); copied at submit */
+    const void *const *fields;   /* NULL: seeded state as fdtd_init_random(seed); else six host
+                                    arrays (host layout, fields_dtype) copied at submit */
+    int fields_dtype;            /* FDTD_F32 or FDTD_F64 when fields != NULL */
+    unsigned long long seed;
+    int keep;                    /* 1: the final state stays resident until fdtd_pool_fetch /
+                                    fdtd_pool_release; 0: its memory is reused at completion */
+} fdtd_request;
+
+typedef enum {
+    FDTD_REQ_QUEUED = 0,   /* waiting for memory */
+    FDTD_REQ_ACTIVE = 1,   /* admitted; sweeps enqueued or pending */
+    FDTD_REQ_DONE = 2,     /* all steps finished on the device */
+    FDTD_REQ_RELEASED = 3, /* released (or cancelled while queued) */
+    FDTD_REQ_FAILED = 4    /* the pool hit a device error */
+} fdtd_request_state;
+
+typedef struct {
+    int state;                        /* fdtd_request_state */
+    double t_submit, t_admit, t_done; /* seconds since pool creation; -1 if not reached */
+    long long steps;
+    size_t bytes;                     /* device bytes held while admitted */
+} fdtd_request_info;
+
+typedef struct {
+    long long submitted, completed, queued, active;
+    long long launches;        /* batched launches enqueued */
+    long long request_sweeps;  /* (request, sweep) pairs enqueued */
+    double cell_updates;       /* cell-steps enqueued */
+    size_t bytes_used, bytes_peak, budget;
+    int peak_active;           /* most requests admitted with sweeps left at once */
+    int failed;
+} fdtd_pool_counters;
+
+/* Defaults: tb_steps 3, max_active 256, backfill 0, device 0; hbm_budget must be set. */
+int fdtd_pool_opts_default(fdtd_pool_opts *opts);
+
+/* Device bytes a request holds while admitted (fields double-buffered, per-node
+   coefficients, and an FP64 staging array when it has host inputs or keep = 1). */
+int fdtd_pool_request_bytes(const fdtd_request *req, size_t *out);
+
+/* Create a pool and start its loop thread. FDTD_E_NOMEM if the budget cannot be allocated. */
+int fdtd_pool_create(const fdtd_pool_opts *opts, fdtd_pool_t *out);
+
+/*
+ * Queue a request; *id is its number (0, 1, 2, ... in submit order). Checks
+ * as fdtd_create (FDTD_E_ARG, FDTD_E_CFL) and FDTD_E_NOMEM if the request can
+ * never fit the budget. Host arrays are copied during the call. Thread-safe.
+ */
+int fdtd_pool_submit(fdtd_pool_t pool, const fdtd_request *req, long long *id);
+
+/*
+ * Block until request id is done (id >= 0) or until every submitted request
+ * has left the queue and the device (id = -1). timeout_s < 0 waits without
+ * limit; otherwise FDTD_E_TIMEOUT when it runs out. FDTD_E_DEVICE if the pool
+ * failed. A queued request behind kept results that are never released waits
+ * for ever. Thread-safe.
+ */
+int fdtd_pool_wait(fdtd_pool_t pool, long long id, double timeout_s);
+
+/* State and timestamps of request id. Thread-safe. */
+int fdtd_pool_info(fdtd_pool_t pool, long long id, fdtd_request_info *out);
+
+/*
+ * Copy the final state (E^n, H^{n-1/2}) of a done keep = 1 request into six
+ * host arrays (host layout, FDTD_F32 or FDTD_F64); waits for the copy. The
+ * request stays resident until fdtd_pool_release.
+ */
+int fdtd_pool_fetch(fdtd_pool_t pool, long long id, void *const host[6], int host_dtype);
+
+/* Free a request's memory (done requests) or cancel it (queued). FDTD_E_STATE while admitted and running. */
+int fdtd_pool_release(fdtd_pool_t pool, long long id);
+
+/* Counters of the pool. Thread-safe. */
+int fdtd_pool_stats(fdtd_pool_t pool, fdtd_pool_counters *out);
+
+/* Stop the loop, wait for enqueued device work, free everything. Queued requests are dropped. */
+int fdtd_pool_destroy(fdtd_pool_t pool);
 
 /*
  * Measurement helper (not part of the method): enqueue a plain 16-byte-wide

@@ -23,7 +23,62 @@
 #include "fdtd.h"
 #include "fdtd_internal.h"
 
+namespace {
+std::string &g_last_error_ref()
+{
+    thread_local std::string msg;
+    return msg;
+}
+}  // namespace
+
 namespace fdtd {
+Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool aux)
+{
+    auto up = [](size_t v, size_t a) { return (v + a - 1) / a * a; };
+    Plan p{};
+    Geom &g = p.g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.px = (int)up((size_t)nx + 1, 64);
+    g.py = ny + 1;
+    g.pz = nz + 1;
+    g.plane = (long long)g.px * g.py;
+    g.box = (long long)up((size_t)g.plane * g.pz + 2 * kGuardElems, 64);
+    p.fesz = (size_t)fesz;
+    p.cesz = fesz == 8 ? 8 : 4;  // 16-bit fields keep FP32 coefficients
+    p.fbox_bytes = up((size_t)g.box * p.fesz, 256);
+    p.cbox_bytes = up((size_t)g.box * p.cesz, 256);
+    size_t off = 0;
+    for (int b = 0; b < 2; ++b)
+        for (int f = 0; f < 6; ++f) {
+            p.off_fields[b][f] = off;
+            off += p.fbox_bytes;
+        }
+    for (int f = 0; f < 3; ++f) {
+        p.off_ce[f] = ce_arr ? off : SIZE_MAX;
+        if (ce_arr) off += p.cbox_bytes;
+    }
+    for (int f = 0; f < 3; ++f) {
+        p.off_ch[f] = ch_arr ? off : SIZE_MAX;
+        if (ch_arr) off += p.cbox_bytes;
+    }
+    if (aux) {
+        p.staging_bytes = up((size_t)(nx + 1) * (ny + 1) * (nz + 1) * sizeof(double), 256);
+        p.off_staging = off;
+        off += p.staging_bytes;
+        p.off_diag = off;
+        off += up((diag_partial_doubles() + 16) * sizeof(double), 256);
+    } else {
+        p.staging_bytes = 0;
+        p.off_staging = p.off_diag = SIZE_MAX;
+    }
+    p.total = off;
+    return p;
+}
+
+void set_last_error(const char *msg) { g_last_error_ref() = msg; }
+
 int xcd_remap()
 {
     static const int v = [] {
@@ -43,7 +98,6 @@ namespace {
 constexpr uint32_t kMagic = 0xFD7D2025u;
 constexpr uint32_t kDead = 0xDEADFD7Du;
 
-thread_local std::string g_last_error;
 
 // Live handles: a destroyed or foreign pointer is rejected without being dereferenced.
 std::mutex g_live_mu;
@@ -63,60 +117,17 @@ int fail(int status, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    g_last_error_ref() = buf;
     return status;
 }
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-struct Plan {
-    Geom g;
-    size_t fesz, cesz;             // bytes per field element, per coefficient element
-    size_t fbox_bytes, cbox_bytes;
-    size_t off_fields[2][6];
-    size_t off_ce[3], off_ch[3];
-    size_t off_staging, staging_bytes;
-    size_t off_diag;
-    size_t total;
-};
+using fdtd::Plan;
 
 Plan make_plan(int nx, int ny, int nz, int storage, bool ce_arr, bool ch_arr)
 {
-    Plan p{};
-    Geom &g = p.g;
-    g.nx = nx;
-    g.ny = ny;
-    g.nz = nz;
-    g.px = (int)round_up((size_t)nx + 1, 64);
-    g.py = ny + 1;
-    g.pz = nz + 1;
-    g.plane = (long long)g.px * g.py;
-    g.box = (long long)round_up((size_t)g.plane * g.pz + 2 * fdtd::kGuardElems, 64);
-    p.fesz = storage == FDTD_F64 ? 8 : storage == FDTD_F32 ? 4 : 2;
-    p.cesz = storage == FDTD_F64 ? 8 : 4;  // 16-bit fields keep FP32 coefficients
-    p.fbox_bytes = round_up((size_t)g.box * p.fesz, 256);
-    p.cbox_bytes = round_up((size_t)g.box * p.cesz, 256);
-    size_t off = 0;
-    for (int b = 0; b < 2; ++b)
-        for (int f = 0; f < 6; ++f) {
-            p.off_fields[b][f] = off;
-            off += p.fbox_bytes;
-        }
-    for (int f = 0; f < 3; ++f) {
-        p.off_ce[f] = ce_arr ? off : SIZE_MAX;
-        if (ce_arr) off += p.cbox_bytes;
-    }
-    for (int f = 0; f < 3; ++f) {
-        p.off_ch[f] = ch_arr ? off : SIZE_MAX;
-        if (ch_arr) off += p.cbox_bytes;
-    }
-    p.staging_bytes = round_up((size_t)(nx + 1) * (ny + 1) * (nz + 1) * sizeof(double), 256);
-    p.off_staging = off;
-    off += p.staging_bytes;
-    p.off_diag = off;
-    off += round_up((fdtd::diag_partial_doubles() + 16) * sizeof(double), 256);
-    p.total = off;
-    return p;
+    return fdtd::make_plan(nx, ny, nz, storage == FDTD_F64 ? 8 : storage == FDTD_F32 ? 4 : 2, ce_arr, ch_arr, true);
 }
 
 }  // namespace
@@ -626,6 +637,30 @@ int fdtd_set_fields_device(fdtd_t h, const void *const dev[6], int dev_dtype)
     return set_fields_common(h, dev, dev_dtype, false);
 }
 
+int fdtd_init_random(fdtd_t h, unsigned long long seed)
+{
+    int st = check(h);
+    if (st)
+        return st;
+    if ((st = use_device(h)))
+        return st;
+    hipError_t e = by_storage(h->storage, [&](auto tag) {
+        using T = decltype(tag);
+        T *a[6], *b[6];
+        for (int f = 0; f < 6; ++f) {
+            a[f] = (T *)h->fld[0][f];
+            b[f] = (T *)h->fld[1][f];
+        }
+        return fdtd::launch_init_random<T>(h->plan.g, seed, a, b, h->stream);
+    });
+    if (e != hipSuccess)
+        return device_fail(h, e, "init_random");
+    h->cur = 0;
+    h->steps = 0;
+    h->fields_set = true;
+    return FDTD_OK;
+}
+
 int fdtd_step(fdtd_t h, long long n)
 {
     int st = check(h);
@@ -807,10 +842,11 @@ const char *fdtd_strerror(int status)
     case FDTD_E_DEVICE: return "device error";
     case FDTD_E_STATE: return "invalid solver state";
     case FDTD_E_UNSUPPORTED: return "unsupported option";
+    case FDTD_E_TIMEOUT: return "wait timed out";
     default: return "unknown status";
     }
 }
 
-const char *fdtd_last_error(void) { return g_last_error.c_str(); }
+const char *fdtd_last_error(void) { return g_last_error_ref().c_str(); }
 
 }  // extern "C"

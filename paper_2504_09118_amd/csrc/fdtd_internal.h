@@ -82,6 +82,46 @@ hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Field
 int temporal_own_rows(int ts, int variant);
 int temporal_width(int variant);
 
+// One request of a batched temporal launch (FP32 fields, variant-0 tiles).
+struct BatchEntry {
+    Geom g;
+    Fields<float> src, dst;
+    Coefs<float> c;
+    int kchunk, ntx, nty, ntiles;
+    int tile_begin;  // first tile of this request in the launch
+};
+
+// Tiling of one request for the batched temporal launch.
+void temporal_tiling(const Geom &g, int ts, int zchunk, int *kchunk, int *ntx, int *nty, int *ntiles);
+
+// One launch advancing every request of a device table by ts steps; entries
+// sorted by tile_begin, ntiles = total tiles. All entries share ts and the
+// presence of Ce / Ch arrays.
+hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, int ts, bool ce_arr, bool ch_arr,
+                                 hipStream_t s);
+
+// Device memory plan of one cavity inside an arena (offsets from a 256-byte
+// aligned base): two state buffers of six boxes, optional per-node Ce / Ch
+// boxes, and (with aux) an FP64 staging array and the diagnostic partials.
+struct Plan {
+    Geom g;
+    size_t fesz, cesz;  // bytes per field element, per coefficient element
+    size_t fbox_bytes, cbox_bytes;
+    size_t off_fields[2][6];
+    size_t off_ce[3], off_ch[3];
+    size_t off_staging, staging_bytes;  // SIZE_MAX / 0 without aux
+    size_t off_diag;
+    size_t total;
+};
+
+// fesz: 8, 4 or 2 bytes; coefficients are FP64 for FP64 fields, else FP32.
+Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool aux);
+
+// Seeded random state (E ~ U[-1,1] from a counter-based SplitMix64, PEC walls,
+// H = 0) written into both state buffers a and b (b may hold nullptrs).
+template <typename T>
+hipError_t launch_init_random(const Geom &g, unsigned long long seed, T *const a[6], T *const b[6], hipStream_t s);
+
 // Tile rows owned per workgroup (rows - 2) and tile width of a slab variant.
 int slab_rows(int variant);
 int slab_width(int variant);
@@ -111,6 +151,9 @@ hipError_t launch_diag(const Geom &g, const Fields<T> &f, const Coefs<typename S
 // Whether the tiled sweeps number their workgroups for the 8 XCDs (1, the
 // default) or in plain launch order (0); FDTD_XCD_REMAP=0 selects the latter.
 int xcd_remap();
+
+// Set the thread-local message fdtd_last_error returns.
+void set_last_error(const char *msg);
 
 // Staggered extents (X, Y, Z) of field f in 0..5.
 __host__ __device__ inline void extents(const Geom &g, int f, int &X, int &Y, int &Z)

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kBlock) k_pack(Geom g, int field, int X, int Y
     int i, j, k;
     unflatten(l, X, Y, i, j, k);
     // 16-bit storage: the host value is rounded to FP32, then to the 16-bit type
-    T v = Store<T>::narrow((typename Store<T>::C)src[l]);
+    T v = Store<T>::narrow(to_compute<T>(src[l]));
     if (e_wall(field, i, j, k, g.nx, g.ny, g.nz))
         v = Store<T>::narrow(0);
     long long o = g.at(i, j, k);

@@ -122,10 +122,12 @@ struct TShape {
     static_assert(2 * NVH * R <= 64 * NHW, "halo lanes do not fit");
 };
 
+// One workgroup's tile: columns [64*tile_x ...), own rows starting at
+// tile_y * (R - 2 TS), planes [zc * kchunk, ...).
 template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR>
-__global__ void __launch_bounds__(1024)
-    k_temporal(Geom g, Fields<S> src, Fields<S> dst, Coefs<typename Store<S>::C> c, int kchunk, int ntx, int nty,
-               int ntiles, int xcd_remap)
+__device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &src, const Fields<S> &dst,
+                                              const Coefs<typename Store<S>::C> &c, int kchunk, int tile_x,
+                                              int tile_y, int zc)
 {
     using T = typename Store<S>::C;  // compute type (FP32 for 16-bit storage)
     using Sh = TShape<TS, RPW>;
@@ -135,15 +137,6 @@ __global__ void __launch_bounds__(1024)
     using vec = typename V2<T>::type;
     __shared__ __attribute__((aligned(16))) T sE[TS][3][RB][LP];  // E input of each stage, plane p_s
     __shared__ __attribute__((aligned(16))) T sH[2][3][RB][LP];   // H of the current stage (alternating)
-
-    const int nper = (ntiles + kXcds - 1) / kXcds;
-    const int b = blockIdx.x;
-    const int t = xcd_remap ? (b % kXcds) * nper + b / kXcds : b;
-    if (t >= ntiles)
-        return;  // the whole workgroup leaves before any barrier
-    const int tile_x = t % ntx;
-    const int tile_y = (t / ntx) % nty;
-    const int zc = t / (ntx * nty);
 
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const long long P = g.plane;
@@ -445,6 +438,50 @@ __global__ void __launch_bounds__(1024)
     }
 }
 
+// XCD-aware tile number of this workgroup: hardware block b runs on XCD b % 8.
+__device__ __forceinline__ int tile_of_block(int ntiles, int xcd_remap)
+{
+    const int nper = (ntiles + kXcds - 1) / kXcds;
+    const int b = blockIdx.x;
+    return xcd_remap ? (b % kXcds) * nper + b / kXcds : b;
+}
+
+template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR>
+__global__ void __launch_bounds__(1024)
+    k_temporal(Geom g, Fields<S> src, Fields<S> dst, Coefs<typename Store<S>::C> c, int kchunk, int ntx, int nty,
+               int ntiles, int xcd_remap)
+{
+    const int t = tile_of_block(ntiles, xcd_remap);
+    if (t >= ntiles)
+        return;  // the whole workgroup leaves before any barrier
+    temporal_tile<S, TS, RPW, CE_ARR, CH_ARR>(g, src, dst, c, kchunk, t % ntx, (t / ntx) % nty, t / (ntx * nty));
+}
+
+// One launch over the tiles of several cavities (continuous batching): the
+// tile number picks the request (entries sorted by tile_begin), then the
+// request's own geometry, buffers and coefficients run the same tile code as
+// a single solve, so each request's bits do not depend on the batch.
+template <int TS, bool CE_ARR, bool CH_ARR>
+__global__ void __launch_bounds__(1024)
+    k_temporal_batch(const BatchEntry *__restrict__ table, int nreq, int ntiles, int xcd_remap)
+{
+    const int t = tile_of_block(ntiles, xcd_remap);
+    if (t >= ntiles)
+        return;
+    int lo = 0, hi = nreq - 1;  // last entry with tile_begin <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].tile_begin <= t)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchEntry e = table[lo];
+    const int u = t - e.tile_begin;
+    temporal_tile<float, TS, 2, CE_ARR, CH_ARR>(e.g, e.src, e.dst, e.c, e.kchunk, u % e.ntx, (u / e.ntx) % e.nty,
+                                                u / (e.ntx * e.nty));
+}
+
 template <typename T, int TS, int RPW>
 hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                      const Coefs<typename Store<T>::C> &c, int zchunk, hipStream_t s)
@@ -482,6 +519,45 @@ int temporal_own_rows(int ts, int variant)
 }
 
 int temporal_width(int variant) { return variant == 1 ? 128 : 64; }
+
+void temporal_tiling(const Geom &g, int ts, int zchunk, int *kchunk, int *ntx, int *nty, int *ntiles)
+{
+    const int own = temporal_own_rows(ts, 0), w = temporal_width(0);
+    zchunk = zchunk < 1 ? 1 : zchunk;
+    *kchunk = (g.nz + zchunk - 1) / zchunk;
+    const int nzc = (g.nz + *kchunk - 1) / *kchunk;
+    *ntx = (g.nx + w - 1) / w;
+    *nty = (g.ny + own - 1) / own;
+    *ntiles = *ntx * *nty * nzc;
+}
+
+hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, int ts, bool ce_arr, bool ch_arr,
+                                 hipStream_t s)
+{
+    if (nreq <= 0 || ntiles <= 0)
+        return hipSuccess;
+    const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
+    dim3 block(64, 16), grid(nblocks);
+    const int rm = xcd_remap();
+#define FDTD_BATCH_LAUNCH(TSV, CEV, CHV) \
+    hipLaunchKernelGGL((k_temporal_batch<TSV, CEV, CHV>), grid, block, 0, s, table, nreq, ntiles, rm)
+#define FDTD_BATCH_TS(TSV)                                    \
+    do {                                                      \
+        if (ce_arr && ch_arr) FDTD_BATCH_LAUNCH(TSV, true, true);   \
+        else if (ce_arr) FDTD_BATCH_LAUNCH(TSV, true, false);       \
+        else if (ch_arr) FDTD_BATCH_LAUNCH(TSV, false, true);       \
+        else FDTD_BATCH_LAUNCH(TSV, false, false);                  \
+    } while (0)
+    switch (ts) {
+    case 1: FDTD_BATCH_TS(1); break;
+    case 2: FDTD_BATCH_TS(2); break;
+    case 3: FDTD_BATCH_TS(3); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef FDTD_BATCH_TS
+#undef FDTD_BATCH_LAUNCH
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,

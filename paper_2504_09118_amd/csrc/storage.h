@@ -77,4 +77,18 @@ struct Store<bf16> {
     __host__ __device__ static bf16 narrow(C v) { return float_to_bf16(v); }
 };
 
+// Source value -> compute type of storage T, rounded once to nearest even.
+// For 16-bit T and an FP64 source the FP32 value is pinned in a register
+// (empty asm) so that the compiler cannot fold FP64 -> FP32 -> FP16 into a
+// single FP64 -> FP16 rounding: 16-bit state is always the rounding of the
+// FP32 state.
+template <typename T, typename S>
+__device__ __forceinline__ typename Store<T>::C to_compute(S v)
+{
+    typename Store<T>::C c = (typename Store<T>::C)v;
+    if constexpr (sizeof(T) == 2 && sizeof(S) == 8)
+        __asm__ volatile("" : "+v"(c));
+    return c;
+}
+
 }  // namespace fdtd

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
-OK, E_ARG, E_CFL, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+OK, E_ARG, E_CFL, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
 F64, F32, F16, BF16 = 0, 1, 2, 3
 STORAGE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 STORAGE_NAMES = {v: k for k, v in STORAGE.items()}
@@ -44,6 +44,51 @@ class _Opts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("arena", ctypes.c_void_p),
         ("arena_bytes", ctypes.c_size_t),
+    ]
+
+
+class _PoolOpts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("device", ctypes.c_int),
+        ("tb_steps", ctypes.c_int),
+        ("max_active", ctypes.c_int),
+        ("backfill", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("arena", ctypes.c_void_p),
+    ]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+        ("steps", ctypes.c_longlong),
+        ("eps_r", ctypes.c_void_p), ("mu_r", ctypes.c_void_p),
+        ("fields", ctypes.c_void_p),
+        ("fields_dtype", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong),
+        ("keep", ctypes.c_int),
+    ]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int),
+        ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+        ("steps", ctypes.c_longlong),
+        ("bytes", ctypes.c_size_t),
+    ]
+
+
+class _PoolCounters(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong),
+        ("queued", ctypes.c_longlong), ("active", ctypes.c_longlong),
+        ("launches", ctypes.c_longlong), ("request_sweeps", ctypes.c_longlong),
+        ("cell_updates", ctypes.c_double),
+        ("bytes_used", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t), ("budget", ctypes.c_size_t),
+        ("peak_active", ctypes.c_int), ("failed", ctypes.c_int),
     ]
 
 
@@ -83,6 +128,21 @@ def load_library():
     lib.fdtd_last_error.restype = ctypes.c_char_p
     lib.fdtd_probe_copy.argtypes = [vp, vp, sz, vp]
     lib.fdtd_probe_copy.restype = i
+    lib.fdtd_init_random.argtypes = [vp, ctypes.c_ulonglong]
+    lib.fdtd_pool_opts_default.argtypes = [ctypes.POINTER(_PoolOpts)]
+    lib.fdtd_pool_request_bytes.argtypes = [ctypes.POINTER(_Request), ctypes.POINTER(sz)]
+    lib.fdtd_pool_create.argtypes = [ctypes.POINTER(_PoolOpts), ctypes.POINTER(vp)]
+    lib.fdtd_pool_submit.argtypes = [vp, ctypes.POINTER(_Request), ctypes.POINTER(ll)]
+    lib.fdtd_pool_wait.argtypes = [vp, ll, ctypes.c_double]
+    lib.fdtd_pool_info.argtypes = [vp, ll, ctypes.POINTER(_RequestInfo)]
+    lib.fdtd_pool_fetch.argtypes = [vp, ll, p6, i]
+    lib.fdtd_pool_release.argtypes = [vp, ll]
+    lib.fdtd_pool_stats.argtypes = [vp, ctypes.POINTER(_PoolCounters)]
+    lib.fdtd_pool_destroy.argtypes = [vp]
+    for name in ("fdtd_init_random", "fdtd_pool_opts_default", "fdtd_pool_request_bytes", "fdtd_pool_create",
+                 "fdtd_pool_submit", "fdtd_pool_wait", "fdtd_pool_info", "fdtd_pool_fetch", "fdtd_pool_release",
+                 "fdtd_pool_stats", "fdtd_pool_destroy"):
+        getattr(lib, name).restype = i
     for name in ("fdtd_opts_default", "fdtd_required_bytes", "fdtd_create", "fdtd_set_fields",
                  "fdtd_set_fields_device", "fdtd_step", "fdtd_get_fields", "fdtd_get_fields_device",
                  "fdtd_get_coefs", "fdtd_sync", "fdtd_diag", "fdtd_query", "fdtd_destroy"):
@@ -223,6 +283,10 @@ class Solver:
         _check(self._lib.fdtd_get_fields(self._h, ptrs, _dtype_code(dtype)))
         return tuple(out)
 
+    def init_random(self, seed: int) -> None:
+        """Seeded random state generated on the device (E ~ U[-1,1] off the walls, H = 0); enqueued."""
+        _check(self._lib.fdtd_init_random(self._h, int(seed) & (2 ** 64 - 1)))
+
     def get_fields_device(self, tensors):
         """Write the state into six contiguous torch CUDA tensors (enqueued, no wait)."""
         import torch
@@ -283,6 +347,120 @@ class Solver:
         try:
             if self._h:
                 self._lib.fdtd_destroy(self._h)
+        except Exception:
+            pass
+
+
+REQUEST_STATES = ("queued", "active", "done", "released", "failed")
+
+
+class Pool:
+    """Continuous-batching pool of cavity solves on one GPU (FP32 storage).
+
+    hbm_budget: device bytes for all admitted requests' state. The pool's loop
+    thread (in the library) admits requests by memory, advances every admitted
+    request by up to tb_steps steps per batched launch, and retires finished
+    ones. stream: as for Solver; None lets the pool create one.
+    """
+
+    def __init__(self, hbm_budget: int, tb_steps: int = 3, max_active: int = 256, backfill: bool = False,
+                 stream=None, device: int = 0):
+        self._lib = load_library()
+        self._h = ctypes.c_void_p(None)
+        opts = _PoolOpts()
+        self._lib.fdtd_pool_opts_default(ctypes.byref(opts))
+        opts.hbm_budget = int(hbm_budget)
+        opts.device = int(device)
+        opts.tb_steps = int(tb_steps)
+        opts.max_active = int(max_active)
+        opts.backfill = int(bool(backfill))
+        if stream is not None:
+            opts.stream = _stream_handle(stream, device)
+        _check(self._lib.fdtd_pool_create(ctypes.byref(opts), ctypes.byref(self._h)))
+
+    @staticmethod
+    def _request(nx, ny, nz, steps, dx, dt, eps_r, mu_r, fields, seed, keep):
+        keep_alive = []
+        eps = _material_array(eps_r, nx, ny, nz)
+        mu = _material_array(mu_r, nx, ny, nz)
+        r = _Request(nx=int(nx), ny=int(ny), nz=int(nz), dx=float(dx),
+                     dt=float(dt if dt is not None else 0.5 / 3 ** 0.5 * dx), steps=int(steps),
+                     eps_r=eps.ctypes.data if eps is not None else None,
+                     mu_r=mu.ctypes.data if mu is not None else None,
+                     seed=int(seed) & (2 ** 64 - 1), keep=int(bool(keep)))
+        keep_alive += [eps, mu]
+        if fields is not None:
+            dtp = np.asarray(fields[0]).dtype
+            arrs = []
+            for a, s in zip(fields, field_shapes(nx, ny, nz)):
+                a = np.ascontiguousarray(a, dtype=dtp)
+                if a.shape != s:
+                    raise ValueError(f"field shape {a.shape} != expected {s}")
+                arrs.append(a)
+            ptrs = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in arrs])
+            keep_alive += [arrs, ptrs]
+            r.fields = ctypes.cast(ptrs, ctypes.c_void_p)
+            r.fields_dtype = _dtype_code(dtp)
+        return r, keep_alive
+
+    @staticmethod
+    def request_bytes(nx, ny, nz, eps_r=False, mu_r=False, host_inputs=False, keep=False) -> int:
+        lib = load_library()
+        r = _Request(nx=int(nx), ny=int(ny), nz=int(nz), dx=1.0, dt=0.1, steps=0,
+                     eps_r=1 if eps_r else None, mu_r=1 if mu_r else None,
+                     fields=1 if host_inputs else None, keep=int(bool(keep)))
+        out = ctypes.c_size_t(0)
+        _check(lib.fdtd_pool_request_bytes(ctypes.byref(r), ctypes.byref(out)))
+        return out.value
+
+    def submit(self, nx, ny, nz, steps, seed=0, dx=1.0, dt=None, eps_r=None, mu_r=None, fields=None,
+               keep=False) -> int:
+        """Queue one cavity solve; returns its id. Host arrays are copied before this returns."""
+        r, _alive = self._request(nx, ny, nz, steps, dx, dt, eps_r, mu_r, fields, seed, keep)
+        rid = ctypes.c_longlong(-1)
+        _check(self._lib.fdtd_pool_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        return rid.value
+
+    def wait(self, rid: int = -1, timeout: float = -1.0) -> None:
+        """Wait for request rid (or all requests with rid = -1)."""
+        _check(self._lib.fdtd_pool_wait(self._h, int(rid), float(timeout)))
+
+    def info(self, rid: int) -> dict:
+        out = _RequestInfo()
+        _check(self._lib.fdtd_pool_info(self._h, int(rid), ctypes.byref(out)))
+        return {"state": REQUEST_STATES[out.state], "t_submit": out.t_submit, "t_admit": out.t_admit,
+                "t_done": out.t_done, "steps": out.steps, "bytes": out.bytes}
+
+    def fetch(self, rid: int, nx: int, ny: int, nz: int, dtype=np.float64):
+        """Final state of a done keep=True request as six host arrays (the request stays resident)."""
+        out = [np.empty(s, dtype=dtype) for s in field_shapes(nx, ny, nz)]
+        ptrs = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in out])
+        _check(self._lib.fdtd_pool_fetch(self._h, int(rid), ptrs, _dtype_code(dtype)))
+        return tuple(out)
+
+    def release(self, rid: int) -> None:
+        _check(self._lib.fdtd_pool_release(self._h, int(rid)))
+
+    def stats(self) -> dict:
+        out = _PoolCounters()
+        _check(self._lib.fdtd_pool_stats(self._h, ctypes.byref(out)))
+        return {name: getattr(out, name) for name, _ in _PoolCounters._fields_}
+
+    def close(self) -> None:
+        if self._h:
+            _check(self._lib.fdtd_pool_destroy(self._h))
+            self._h = ctypes.c_void_p(None)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if self._h:
+                self._lib.fdtd_pool_destroy(self._h)
         except Exception:
             pass
 

@@ -121,3 +121,79 @@ def test_strerror():
     for code in (F.OK, F.E_ARG, F.E_CFL, F.E_NOMEM, F.E_DEVICE, F.E_STATE, F.E_UNSUPPORTED):
         assert lib.fdtd_strerror(code)
     assert lib.fdtd_strerror(F.E_CFL) != lib.fdtd_strerror(F.E_ARG)
+
+
+def test_strerror_timeout():
+    lib = F.load_library()
+    assert b"time" in lib.fdtd_strerror(F.E_TIMEOUT)
+
+
+def test_pool_invalid_handles_are_rejected():
+    lib = F.load_library()
+    bogus = ctypes.c_void_p(0x5678)
+    req = F._Request(nx=8, ny=8, nz=8, dx=1.0, dt=0.25, steps=10)
+    rid = ctypes.c_longlong(-1)
+    assert lib.fdtd_pool_submit(None, ctypes.byref(req), ctypes.byref(rid)) == F.E_STATE
+    assert lib.fdtd_pool_submit(bogus, ctypes.byref(req), ctypes.byref(rid)) == F.E_STATE
+    assert lib.fdtd_pool_wait(bogus, -1, 0.0) == F.E_STATE
+    info = F._RequestInfo()
+    assert lib.fdtd_pool_info(bogus, 0, ctypes.byref(info)) == F.E_STATE
+    ptrs = (ctypes.c_void_p * 6)()
+    assert lib.fdtd_pool_fetch(bogus, 0, ptrs, F.F32) == F.E_STATE
+    assert lib.fdtd_pool_release(bogus, 0) == F.E_STATE
+    cnt = F._PoolCounters()
+    assert lib.fdtd_pool_stats(bogus, ctypes.byref(cnt)) == F.E_STATE
+    assert lib.fdtd_pool_destroy(bogus) == F.E_STATE
+    assert lib.fdtd_pool_destroy(None) == F.E_STATE
+    assert lib.fdtd_init_random(bogus, 1) == F.E_STATE
+
+
+def test_pool_create_validates_options():
+    lib = F.load_library()
+    opts = F._PoolOpts()
+    assert lib.fdtd_pool_opts_default(ctypes.byref(opts)) == F.OK
+    assert opts.tb_steps == 3 and opts.max_active == 256 and opts.backfill == 0 and opts.hbm_budget == 0
+    h = ctypes.c_void_p(None)
+    assert lib.fdtd_pool_create(ctypes.byref(opts), ctypes.byref(h)) == F.E_ARG  # no budget
+    opts.hbm_budget = 1 << 30
+    opts.tb_steps = 4
+    assert lib.fdtd_pool_create(ctypes.byref(opts), ctypes.byref(h)) == F.E_ARG
+    opts.tb_steps = 3
+    opts.max_active = -2
+    assert lib.fdtd_pool_create(ctypes.byref(opts), ctypes.byref(h)) == F.E_ARG
+    assert not h.value
+    assert lib.fdtd_pool_create(None, ctypes.byref(h)) == F.E_ARG
+
+
+def test_pool_request_bytes():
+    px = 128  # nx + 1 = 65 rounded up to 64 elements
+    box = px * 49 * 41 * 4
+    vac = F.Pool.request_bytes(64, 48, 40)
+    eps = F.Pool.request_bytes(64, 48, 40, eps_r=True)
+    keep = F.Pool.request_bytes(64, 48, 40, keep=True)
+    host = F.Pool.request_bytes(64, 48, 40, host_inputs=True)
+    assert 12 * box <= vac < 12 * box + 12 * 4096
+    assert eps - vac >= 3 * box
+    staging = 65 * 49 * 41 * 8
+    assert keep - vac >= staging and host == keep
+    # a standalone solver also carries staging and diagnostic space
+    assert F.required_bytes(64, 48, 40) > vac
+    with pytest.raises(F.FdtdError):
+        F.Pool.request_bytes(64, 1, 40)
+
+
+def test_serving_request_distribution():
+    from paper_2504_09118_amd import serve
+    import cavity_inputs as ci
+
+    specs = serve.draw_requests(4000, 4)
+    d = np.array([s[:3] for s in specs])
+    k = np.array([s[3] for s in specs])
+    assert set(np.unique(d)) == set(range(48, 385, 16))
+    assert k.min() >= 200 and k.max() <= 2000 and abs(k.mean() - 1100) < 30
+    # dims drawn independently per axis: non-cubic requests dominate
+    assert np.mean((d[:, 0] == d[:, 1]) & (d[:, 1] == d[:, 2])) < 0.01
+    # per-request seeds are SplitMix64 outputs of the run seed (same generator as the inputs module)
+    ref = ci.splitmix64(4, np.arange(5, dtype=np.uint64))
+    assert [s[4] for s in specs[:5]] == [int(x) for x in ref]
+    assert abs(serve.mean_work() - 216.0 ** 3 * 1100) < 1
