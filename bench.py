@@ -6,8 +6,10 @@ Inputs (fields, coefficients) are resident in HBM before the timed region.
 
 Prints one JSON line with the throughput in Gcell-updates/s, the roofline of
 the dominant kernel (algorithmic bytes per launch / average launch duration,
-timed with events on the stream the kernels run on) and the FP64 CPU oracle
-timed on the host on a bounded sample of the same workload.
+timed with events on the stream the kernels run on), the serving latency
+(p50/p99 of a Poisson stream of mixed-size cavity solves through the
+continuous-batching pool) and the FP64 CPU oracle timed on the host on a
+bounded sample of the same workload.
 """
 
 from __future__ import annotations
@@ -79,6 +81,10 @@ def main() -> int:
                     help="device field storage (16-bit fields compute in FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-load", type=float, default=0.9, help="offered load, fraction of saturation")
+    ap.add_argument("--serving-budget-gib", type=float, default=16.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -175,6 +181,12 @@ def main() -> int:
     }
 
     result["copy_probe"] = copy_probe(stream)
+    if not args.no_serving:
+        from paper_2504_09118_amd import serve
+
+        result["serving"] = serve.bench_point(int(args.serving_budget_gib * 2 ** 30), load=args.serving_load,
+                                              n_requests=args.serving_requests, stream=stream,
+                                              log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(e, eps, nx, ny, nz, dx, dt, args.cpu_steps)
     print(json.dumps(result), flush=True)

@@ -185,3 +185,30 @@ def uniform_cell_eps(nx: int, ny: int, nz: int, seed: int, lo: float = 1.0, hi: 
 def courant_dt(dx: float = 1.0, courant: float = 0.5 / math.sqrt(3.0)) -> float:
     """dt = S dx in units where c = eps0 = mu0 = 1."""
     return courant * dx
+
+
+def distinct_nodes(seed: int, count: int, lo: tuple, hi: tuple) -> list:
+    """`count` distinct integer points (i, j, k) with lo <= point < hi per axis.
+
+    Candidate c takes its three coordinates from counters 3c .. 3c+2 of the
+    seed's stream (coordinate = lo + floor(u * (hi - lo))); repeats are
+    skipped, so the list is a deterministic function of the seed.
+    """
+    out, seen, c = [], set(), 0
+    span = [h - l for l, h in zip(lo, hi)]
+    if count > int(np.prod(span)):
+        raise ValueError("more nodes than the box holds")
+    while len(out) < count:
+        u = unit_uniform(seed, 3 * c, 3)
+        p = tuple(int(l + min(s - 1, math.floor(v * s))) for l, s, v in zip(lo, span, u))
+        c += 1
+        if p not in seen:
+            seen.add(p)
+            out.append(p)
+    return out
+
+
+def gaussian_pulse(nsteps: int, center: float = 60.0, width: float = 20.0) -> np.ndarray:
+    """w[n-1] = exp(-((n - center) / width)^2) for steps n = 1 .. nsteps."""
+    n = np.arange(1, nsteps + 1, dtype=np.float64)
+    return np.exp(-(((n - center) / width) ** 2))

@@ -136,6 +136,41 @@ def serving_sweep(budget_bytes: int, fractions, n_per_rate: int = 200, n_burst: 
     }
 
 
+def bench_point(budget_bytes: int, load: float = 0.9, n_requests: int = 200, n_burst: int = 100,
+                n_serial: int = 40, seed: int = 4, stream=None, log=None) -> dict:
+    """One serving measurement: saturation burst, a Poisson run at `load` x saturation, and the
+    throughput of the same pool admitting one request at a time (a plain queue, no batching)."""
+    with Pool(budget_bytes, stream=stream) as pool:
+        run_burst(pool, 8, seed + 1000)
+        sat = run_burst(pool, n_burst, seed + 2000)
+        rate = load * sat["requests_per_s"]
+        pt = run_poisson(pool, rate, n_requests, seed)
+    if log:
+        log(f"serve: saturation {sat['requests_per_s']:.2f} req/s; load {load}: p50 {pt['p50_ms']:.1f} ms, "
+            f"p99 {pt['p99_ms']:.1f} ms")
+    with Pool(budget_bytes, max_active=1, stream=stream) as pool:
+        run_burst(pool, 4, seed + 1000)
+        serial = run_burst(pool, n_serial, seed + 3000)
+    if log:
+        log(f"serve: one request at a time {serial['gcell_per_s']:.1f} Gcell/s")
+    return {
+        "workload": "Poisson stream of PEC cavity solves, dims i.i.d. {48..384 step 16}, steps U[200,2000], "
+                    "FP32, seeded random init, vacuum",
+        "hbm_budget_bytes": budget_bytes,
+        "load": load,
+        "offered_req_per_s": round(rate, 3),
+        "requests": pt["requests"],
+        "p50_ms": round(pt["p50_ms"], 2),
+        "p99_ms": round(pt["p99_ms"], 2),
+        "queue_wait_p99_ms": round(pt["queue_wait_p99_ms"], 2),
+        "gcell_per_s": round(pt["gcell_per_s"], 2),
+        "requests_per_s": round(pt["requests_per_s"], 3),
+        "saturation_req_per_s": round(sat["requests_per_s"], 3),
+        "saturation_gcell_per_s": round(sat["gcell_per_s"], 2),
+        "one_at_a_time_gcell_per_s": round(serial["gcell_per_s"], 2),
+    }
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--budget-gib", type=float, default=16.0)
