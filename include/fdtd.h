@@ -211,6 +211,60 @@ void *fdtd_stream(fdtd_t h);
 int fdtd_destroy(fdtd_t h);
 
 /*
+ * ---- Adjoint: gradient of a driven-cavity probe objective ----
+ *
+ * Ampere's law of Sec. 2 (Eq. 2) carries a current density that the
+ * source-free cavity update drops; here it drives the cavity as a point
+ * source. Starting from the solver's current state (E^0, H^{-1/2}), each of
+ * the N steps is a leapfrog step (Sec. 2.1 algorithm listing), then w[n-1] is
+ * added to the source node, then the probe nodes are read:
+ *     J = sum_{n=1..N} sum_p (E^n at probe p)^2.
+ * fdtd_adjoint_backward returns dJ/d eps_r per cell by the discrete adjoint:
+ * the same curl stencils run in reverse time with the coefficient inside the
+ * curl (the E curl is minus the transpose of the H curl), accumulating
+ * dJ/dCe = sum_n lam^{n+1} (L H^{n+1/2}) per edge in FP64, then
+ * dJ/d eps_cell = sum over the cell's 12 edges of dJ/dCe * (-Ce^2 dx/dt / 4)
+ * (Ce = dt/(dx * mean eps of the edge's four cells)). The forward pass stores
+ * (E^n, H^{n-1/2}) every checkpoint_every steps; the backward pass recomputes
+ * each segment from its checkpoint (checkpoint-and-recompute), so device
+ * memory is ceil(N/K) states + K H-fields, not N.
+ */
+typedef struct fdtd_adjoint *fdtd_adjoint_t;
+
+typedef struct {
+    int src_field;            /* E component of the source node (FDTD_EX..FDTD_EZ), or -1 for none */
+    int src_i, src_j, src_k;  /* source node, interior (not tangential to a wall) */
+    const double *waveform;   /* nsteps values; waveform[n-1] is added after the E update of step n */
+    int nprobes;
+    const int *probes;        /* 4 ints per probe: E component, i, j, k (interior E nodes) */
+    long long nsteps;         /* N >= 1 */
+    int checkpoint_every;     /* K >= 1 (0: 50) */
+} fdtd_adjoint_problem;
+
+/*
+ * Bind an adjoint problem to a solver created with per-cell eps_r (FP32 or
+ * FP64 storage; FDTD_E_UNSUPPORTED otherwise). Host arrays are copied.
+ * Allocates the checkpoint, history and adjoint buffers (FDTD_E_NOMEM). The
+ * solver must outlive the handle; it is not thread-safe with it.
+ */
+int fdtd_adjoint_create(fdtd_t solver, const fdtd_adjoint_problem *problem, fdtd_adjoint_t *out);
+
+/* Run the N driven steps from the solver's current state, storing checkpoints; *J receives J. Waits. */
+int fdtd_adjoint_forward(fdtd_adjoint_t adj, double *J);
+
+/*
+ * Reverse pass of the last forward: grad_eps receives dJ/d eps_r per cell
+ * (host, nx*ny*nz doubles, x-fastest). lam0, if not NULL, receives dJ/dE^0
+ * (three host arrays in the Ex, Ey, Ez host layout, lam0_dtype FDTD_F32 or
+ * FDTD_F64). The solver's state afterwards is that of the first recomputed
+ * segment's end (not E^N). Waits.
+ */
+int fdtd_adjoint_backward(fdtd_adjoint_t adj, double *grad_eps, void *const lam0[3], int lam0_dtype);
+
+/* Free the adjoint buffers (waits for the solver's stream). */
+int fdtd_adjoint_destroy(fdtd_adjoint_t adj);
+
+/*
  * ---- Serving pool: continuous batching of many cavity solves ----
  *
  * A pool owns one block of device memory (hbm_budget bytes) and a host thread

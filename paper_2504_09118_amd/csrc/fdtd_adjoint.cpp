@@ -1,0 +1,421 @@
+// Adjoint (reverse-time) gradient of a driven-cavity probe objective with
+// respect to per-cell permittivity (declared and documented in include/fdtd.h).
+//
+// Forward: N single leapfrog steps of the solver, each followed by the point
+// source and the probe reads; the state (E^n, H^{n-1/2}) is copied to a
+// checkpoint every K steps. Backward: for each segment of K steps, last one
+// first, the segment is recomputed from its checkpoint keeping every
+// H^{n+1/2}, then walked in reverse with the adjoint sweeps. Device memory:
+// ceil(N/K) checkpoints of six boxes, K history slots of three H boxes, the
+// adjoint fields (six boxes), FP64 dJ/dCe (three boxes) and the FP64 cell
+// gradient.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <unordered_set>
+#include <vector>
+
+#include "fdtd.h"
+#include "fdtd_internal.h"
+#include "solver.h"
+
+using fdtd::Coefs;
+using fdtd::Fields;
+using fdtd::Geom;
+
+namespace {
+
+constexpr uint32_t kAdjMagic = 0xFD7DAD01u;
+
+std::mutex g_adj_mu;
+std::unordered_set<const void *> g_adj;
+
+int afail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int afail(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fdtd::set_last_error(buf);
+    return status;
+}
+
+// Interior (updated) E node of component f: not tangential to a wall.
+bool interior_e(const fdtd_solver *s, int f, int i, int j, int k)
+{
+    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    switch (f) {
+    case 0: return i >= 0 && i < nx && j >= 1 && j < ny && k >= 1 && k < nz;
+    case 1: return i >= 1 && i < nx && j >= 0 && j < ny && k >= 1 && k < nz;
+    case 2: return i >= 1 && i < nx && j >= 1 && j < ny && k >= 0 && k < nz;
+    default: return false;
+    }
+}
+
+}  // namespace
+
+struct fdtd_adjoint {
+    uint32_t magic;
+    fdtd_t s;
+    int sf;
+    long long so;
+    std::vector<double> wave;
+    int np;
+    std::vector<int> pf;
+    std::vector<long long> po;
+    long long N;
+    int K, nseg;
+    char *mem;
+    size_t guard, fbox;
+    int *d_pf;
+    long long *d_po;
+    double *d_rec, *d_J, *d_grad;
+    char *ckpt, *hist;
+    void *adj[6];  // lam Ex Ey Ez, mu Hx Hy Hz (element (0,0,0) of each box)
+    double *gce[3];
+    bool forward_done;
+};
+
+namespace {
+
+int acheck(fdtd_adjoint_t a)
+{
+    std::lock_guard<std::mutex> lk(g_adj_mu);
+    if (!a || !g_adj.count(a) || a->magic != kAdjMagic)
+        return afail(FDTD_E_STATE, "invalid or destroyed adjoint handle");
+    return FDTD_OK;
+}
+
+// Start of the box that holds element (0,0,0) at p.
+char *box_of(const fdtd_adjoint *a, void *p) { return (char *)p - a->guard; }
+
+template <typename T>
+Fields<T> state_of(fdtd_t s)
+{
+    Fields<T> f;
+    for (int q = 0; q < 6; ++q) f.f[q] = (T *)s->fld[s->cur][q];
+    return f;
+}
+
+template <typename T>
+Coefs<T> coefs_of(fdtd_t s)
+{
+    Coefs<T> c;
+    for (int q = 0; q < 3; ++q) {
+        c.ce[q] = (const T *)s->ce[q];
+        c.ch[q] = (const T *)s->ch[q];
+    }
+    c.ce_s = (T)s->ce_s;
+    c.ch_s = (T)s->ch_s;
+    return c;
+}
+
+// One driven step: leapfrog step, point source, probes (rec_row null: none).
+template <typename T>
+int driven_step(fdtd_adjoint_t a, long long n, double *rec_row)
+{
+    fdtd_t s = a->s;
+    if (int st = fdtd_step(s, 1))
+        return st;
+    hipError_t e = fdtd::launch_source_probe<T>(state_of<T>(s), a->sf, a->so, a->sf >= 0 ? a->wave[n] : 0.0,
+                                                rec_row ? a->np : 0, a->d_pf, a->d_po, rec_row, a->d_J, s->stream);
+    if (e != hipSuccess)
+        return fdtd::solver_device_fail(s, e, "source/probe kernel");
+    return FDTD_OK;
+}
+
+hipError_t copy_state(fdtd_adjoint_t a, char *dst, bool to_solver)
+{
+    fdtd_t s = a->s;
+    for (int q = 0; q < 6; ++q) {
+        char *box = box_of(a, s->fld[s->cur][q]);
+        char *slot = dst + (size_t)q * a->fbox;
+        hipError_t e = to_solver ? hipMemcpyAsync(box, slot, a->fbox, hipMemcpyDeviceToDevice, s->stream)
+                                 : hipMemcpyAsync(slot, box, a->fbox, hipMemcpyDeviceToDevice, s->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T>
+int forward_impl(fdtd_adjoint_t a, double *J)
+{
+    fdtd_t s = a->s;
+    hipError_t e = hipMemsetAsync(a->d_J, 0, sizeof(double), s->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(a->d_rec, 0, (size_t)(a->N + 1) * a->np * sizeof(double), s->stream);
+    if (e != hipSuccess)
+        return fdtd::solver_device_fail(s, e, "adjoint forward");
+    for (long long n = 0; n < a->N; ++n) {
+        if (n % a->K == 0 && (e = copy_state(a, a->ckpt + (size_t)(n / a->K) * 6 * a->fbox, false)) != hipSuccess)
+            return fdtd::solver_device_fail(s, e, "checkpoint");
+        if (int st = driven_step<T>(a, n, a->d_rec + (size_t)(n + 1) * a->np))
+            return st;
+    }
+    double hJ = 0.0;
+    e = hipMemcpyAsync(&hJ, a->d_J, sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess)
+        return fdtd::solver_device_fail(s, e, "adjoint forward");
+    *J = hJ;
+    a->forward_done = true;
+    return FDTD_OK;
+}
+
+template <typename T>
+int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_dtype)
+{
+    fdtd_t s = a->s;
+    const Geom &g = s->plan.g;
+    Fields<T> adj;
+    for (int q = 0; q < 6; ++q) adj.f[q] = (T *)a->adj[q];
+    const Coefs<T> c = coefs_of<T>(s);
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < 6 && e == hipSuccess; ++q)
+        e = hipMemsetAsync(box_of(a, a->adj[q]), 0, a->fbox, s->stream);
+    for (int q = 0; q < 3 && e == hipSuccess; ++q)
+        e = hipMemsetAsync((char *)a->gce[q] - fdtd::kGuardElems * sizeof(double), 0,
+                           (size_t)g.box * sizeof(double), s->stream);
+    if (e == hipSuccess)
+        e = fdtd::launch_adj_probe<T>(adj, a->np, a->d_pf, a->d_po, a->d_rec + (size_t)a->N * a->np, s->stream);
+    if (e != hipSuccess)
+        return fdtd::solver_device_fail(s, e, "adjoint setup");
+    for (int seg = a->nseg - 1; seg >= 0; --seg) {
+        const long long n0 = (long long)seg * a->K, n1 = std::min(a->N, n0 + a->K);
+        if ((e = copy_state(a, a->ckpt + (size_t)seg * 6 * a->fbox, true)) != hipSuccess)
+            return fdtd::solver_device_fail(s, e, "restore checkpoint");
+        for (long long n = n0; n < n1; ++n) {
+            if (int st = driven_step<T>(a, n, nullptr))
+                return st;
+            char *slot = a->hist + (size_t)(n - n0) * 3 * a->fbox;
+            for (int q = 0; q < 3 && e == hipSuccess; ++q)
+                e = hipMemcpyAsync(slot + (size_t)q * a->fbox, box_of(a, s->fld[s->cur][3 + q]), a->fbox,
+                                   hipMemcpyDeviceToDevice, s->stream);
+            if (e != hipSuccess)
+                return fdtd::solver_device_fail(s, e, "history copy");
+        }
+        for (long long n = n1 - 1; n >= n0; --n) {
+            char *slot = a->hist + (size_t)(n - n0) * 3 * a->fbox;
+            const T *h[3];
+            for (int q = 0; q < 3; ++q) h[q] = (const T *)(slot + (size_t)q * a->fbox + a->guard);
+            e = fdtd::launch_adj_step<T>(g, adj, c, h, a->gce, s->stream);
+            if (e == hipSuccess && n >= 1)
+                e = fdtd::launch_adj_probe<T>(adj, a->np, a->d_pf, a->d_po, a->d_rec + (size_t)n * a->np,
+                                              s->stream);
+            if (e != hipSuccess)
+                return fdtd::solver_device_fail(s, e, "adjoint step");
+        }
+    }
+    e = fdtd::launch_grad_eps<T>(g, c, a->gce, s->dx / s->dt, a->d_grad, s->stream);
+    const size_t ncell = (size_t)s->nx * s->ny * s->nz;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(grad, a->d_grad, ncell * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    for (int q = 0; q < 3 && lam0 && e == hipSuccess; ++q) {
+        int X, Y, Z;
+        fdtd::extents(g, q, X, Y, Z);
+        const size_t n = (size_t)X * Y * Z;
+        if (lam0_dtype == FDTD_F64) {
+            e = fdtd::launch_unpack<T, double>(g, q, (const T *)a->adj[q], (double *)s->staging, s->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(lam0[q], s->staging, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+        } else {
+            e = fdtd::launch_unpack<T, float>(g, q, (const T *)a->adj[q], (float *)s->staging, s->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(lam0[q], s->staging, n * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+        }
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s->stream);  // staging is reused by the next component
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess)
+        return fdtd::solver_device_fail(s, e, "adjoint gradient");
+    return FDTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t *out)
+{
+    if (int st = fdtd::solver_check(s))
+        return st;
+    if (!p || !out)
+        return afail(FDTD_E_ARG, "NULL argument");
+    if (s->storage != FDTD_F32 && s->storage != FDTD_F64)
+        return afail(FDTD_E_UNSUPPORTED, "the adjoint is built for FP32 and FP64 storage");
+    if (!s->ce_arr)
+        return afail(FDTD_E_UNSUPPORTED, "the permittivity gradient needs a solver created with per-cell eps_r");
+    if (p->nsteps < 1)
+        return afail(FDTD_E_ARG, "nsteps must be >= 1 (got %lld)", p->nsteps);
+    const int K = p->checkpoint_every ? p->checkpoint_every : 50;
+    if (K < 1)
+        return afail(FDTD_E_ARG, "checkpoint_every must be >= 1 (got %d)", p->checkpoint_every);
+    if (p->src_field >= 0) {
+        if (!interior_e(s, p->src_field, p->src_i, p->src_j, p->src_k))
+            return afail(FDTD_E_ARG, "source (%d: %d %d %d) is not an interior E node", p->src_field, p->src_i,
+                         p->src_j, p->src_k);
+        if (!p->waveform)
+            return afail(FDTD_E_ARG, "NULL waveform");
+        for (long long n = 0; n < p->nsteps; ++n)
+            if (!std::isfinite(p->waveform[n]))
+                return afail(FDTD_E_ARG, "waveform[%lld] is not finite", n);
+    }
+    if (p->nprobes < 0 || (p->nprobes > 0 && !p->probes))
+        return afail(FDTD_E_ARG, "bad probe list");
+    for (int q = 0; q < p->nprobes; ++q) {
+        const int *pr = p->probes + 4 * q;
+        if (!interior_e(s, pr[0], pr[1], pr[2], pr[3]))
+            return afail(FDTD_E_ARG, "probe %d (%d: %d %d %d) is not an interior E node", q, pr[0], pr[1], pr[2],
+                         pr[3]);
+    }
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess)
+        return afail(FDTD_E_DEVICE, "hipSetDevice: %s", hipGetErrorString(e));
+
+    fdtd_adjoint *a = new fdtd_adjoint();
+    a->magic = kAdjMagic;
+    a->s = s;
+    const Geom &g = s->plan.g;
+    a->sf = p->src_field >= 0 ? p->src_field : -1;
+    a->so = a->sf >= 0 ? g.at(p->src_i, p->src_j, p->src_k) : 0;
+    if (a->sf >= 0)
+        a->wave.assign(p->waveform, p->waveform + p->nsteps);
+    a->np = p->nprobes;
+    for (int q = 0; q < p->nprobes; ++q) {
+        const int *pr = p->probes + 4 * q;
+        a->pf.push_back(pr[0]);
+        a->po.push_back(g.at(pr[1], pr[2], pr[3]));
+    }
+    a->N = p->nsteps;
+    a->K = K;
+    a->nseg = (int)((p->nsteps + K - 1) / K);
+    a->guard = (size_t)fdtd::kGuardElems * s->plan.fesz;
+    a->fbox = s->plan.fbox_bytes;
+    const size_t gbox = ((size_t)g.box * sizeof(double) + 255) / 256 * 256;
+    const size_t ncell = (size_t)s->nx * s->ny * s->nz;
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t off = 0;
+    const size_t o_ckpt = off;
+    off += (size_t)a->nseg * 6 * a->fbox;
+    const size_t o_hist = off;
+    off += (size_t)K * 3 * a->fbox;
+    const size_t o_adj = off;
+    off += 6 * a->fbox;
+    const size_t o_gce = off;
+    off += 3 * gbox;
+    const size_t o_grad = off;
+    off += up(ncell * sizeof(double));
+    const size_t o_rec = off;
+    off += up((size_t)(a->N + 1) * std::max(1, a->np) * sizeof(double));
+    const size_t o_j = off;
+    off += 256;
+    const size_t o_pf = off;
+    off += up((size_t)std::max(1, a->np) * sizeof(int));
+    const size_t o_po = off;
+    off += up((size_t)std::max(1, a->np) * sizeof(long long));
+    e = hipMalloc((void **)&a->mem, off);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete a;
+        return afail(FDTD_E_NOMEM, "adjoint needs %zu device bytes: %s", off, hipGetErrorString(e));
+    }
+    a->ckpt = a->mem + o_ckpt;
+    a->hist = a->mem + o_hist;
+    for (int q = 0; q < 6; ++q) a->adj[q] = a->mem + o_adj + (size_t)q * a->fbox + a->guard;
+    for (int q = 0; q < 3; ++q)
+        a->gce[q] = (double *)(a->mem + o_gce + (size_t)q * gbox) + fdtd::kGuardElems;
+    a->d_grad = (double *)(a->mem + o_grad);
+    a->d_rec = (double *)(a->mem + o_rec);
+    a->d_J = (double *)(a->mem + o_j);
+    a->d_pf = (int *)(a->mem + o_pf);
+    a->d_po = (long long *)(a->mem + o_po);
+    if (a->np) {
+        e = hipMemcpyAsync(a->d_pf, a->pf.data(), a->np * sizeof(int), hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(a->d_po, a->po.data(), a->np * sizeof(long long), hipMemcpyHostToDevice, s->stream);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(a->mem);
+        delete a;
+        return afail(FDTD_E_DEVICE, "adjoint setup: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_adj_mu);
+        g_adj.insert(a);
+    }
+    *out = a;
+    return FDTD_OK;
+}
+
+int fdtd_adjoint_forward(fdtd_adjoint_t a, double *J)
+{
+    if (int st = acheck(a))
+        return st;
+    if (int st = fdtd::solver_check(a->s))
+        return st;
+    if (!J)
+        return afail(FDTD_E_ARG, "NULL J");
+    if (!a->s->fields_set)
+        return afail(FDTD_E_STATE, "fields were never set");
+    if (hipSetDevice(a->s->device) != hipSuccess)
+        return afail(FDTD_E_DEVICE, "hipSetDevice failed");
+    a->forward_done = false;
+    return a->s->storage == FDTD_F64 ? forward_impl<double>(a, J) : forward_impl<float>(a, J);
+}
+
+int fdtd_adjoint_backward(fdtd_adjoint_t a, double *grad_eps, void *const lam0[3], int lam0_dtype)
+{
+    if (int st = acheck(a))
+        return st;
+    if (int st = fdtd::solver_check(a->s))
+        return st;
+    if (!grad_eps)
+        return afail(FDTD_E_ARG, "NULL grad_eps");
+    if (lam0 && (!lam0[0] || !lam0[1] || !lam0[2]))
+        return afail(FDTD_E_ARG, "NULL pointer in lam0");
+    if (lam0 && lam0_dtype != FDTD_F32 && lam0_dtype != FDTD_F64)
+        return afail(FDTD_E_ARG, "unsupported lam0 dtype %d", lam0_dtype);
+    if (!a->forward_done)
+        return afail(FDTD_E_STATE, "backward needs a completed forward");
+    if (hipSetDevice(a->s->device) != hipSuccess)
+        return afail(FDTD_E_DEVICE, "hipSetDevice failed");
+    return a->s->storage == FDTD_F64 ? backward_impl<double>(a, grad_eps, lam0, lam0_dtype)
+                                     : backward_impl<float>(a, grad_eps, lam0, lam0_dtype);
+}
+
+int fdtd_adjoint_destroy(fdtd_adjoint_t a)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_adj_mu);
+        if (!a || g_adj.erase(a) == 0)
+            return afail(FDTD_E_STATE, "invalid or destroyed adjoint handle");
+    }
+    hipError_t e = hipSuccess;
+    if (a->mem) {
+        // the solver's stream may still read the buffers
+        if (fdtd::solver_check(a->s) == FDTD_OK)
+            e = hipStreamSynchronize(a->s->stream);
+        else
+            e = hipDeviceSynchronize();
+        (void)hipFree(a->mem);
+    }
+    a->magic = 0;
+    delete a;
+    if (e != hipSuccess)
+        return afail(FDTD_E_DEVICE, "adjoint destroy: %s", hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+}  // extern "C"

@@ -22,6 +22,7 @@
 
 #include "fdtd.h"
 #include "fdtd_internal.h"
+#include "solver.h"
 
 namespace {
 std::string &g_last_error_ref()
@@ -132,27 +133,6 @@ Plan make_plan(int nx, int ny, int nz, int storage, bool ce_arr, bool ch_arr)
 
 }  // namespace
 
-struct fdtd_solver {
-    uint32_t magic;
-    int nx, ny, nz;
-    double dx, dt;
-    int storage, kernel, tb, device, zchunk, tzchunk, variant, tvariant;
-    hipStream_t stream;
-    bool own_stream;
-    char *arena;
-    size_t arena_bytes;
-    bool own_arena;
-    Plan plan;
-    void *fld[2][6];
-    void *ce[3], *ch[3];
-    bool ce_arr, ch_arr;
-    double ce_s, ch_s;
-    void *staging;
-    double *diag;
-    int cur;
-    long long steps, sweeps;
-    bool failed, fields_set;
-};
 
 namespace {
 
@@ -413,6 +393,11 @@ int get_common(fdtd_t h, void *const dst[6], int dtype, bool staged, void *const
 }
 
 }  // namespace
+
+namespace fdtd {
+int solver_check(fdtd_t h) { return check(h); }
+int solver_device_fail(fdtd_t h, hipError_t e, const char *what) { return device_fail(h, e, what); }
+}  // namespace fdtd
 
 extern "C" {
 

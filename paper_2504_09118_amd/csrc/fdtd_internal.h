@@ -122,6 +122,25 @@ Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool 
 template <typename T>
 hipError_t launch_init_random(const Geom &g, unsigned long long seed, T *const a[6], T *const b[6], hipStream_t s);
 
+// Driven-cavity adjoint (FP32 / FP64 storage). Point source: add w to node
+// so of component sf (sf < 0: none); probes: record E at (pf, po) into
+// rec_row and add their squares to *J (rec_row null: no probes).
+template <typename T>
+hipError_t launch_source_probe(const Fields<T> &f, int sf, long long so, double w, int np, const int *pf,
+                               const long long *po, double *rec_row, double *J, hipStream_t s);
+// lam += 2 rec_row at the probe nodes.
+template <typename T>
+hipError_t launch_adj_probe(const Fields<T> &lam, int np, const int *pf, const long long *po, const double *rec_row,
+                            hipStream_t s);
+// One reverse step: a = (lam Ex Ey Ez, mu Hx Hy Hz); hist = H^{n+1/2}; gce += lam (L hist).
+template <typename T>
+hipError_t launch_adj_step(const Geom &g, const Fields<T> &a, const Coefs<T> &c, const T *const hist[3],
+                           double *const gce[3], hipStream_t s);
+// dJ/d eps per cell (dense x-fastest nx*ny*nz doubles) from dJ/dCe per edge.
+template <typename T>
+hipError_t launch_grad_eps(const Geom &g, const Coefs<T> &c, double *const gce[3], double dx_over_dt, double *out,
+                           hipStream_t s);
+
 // Tile rows owned per workgroup (rows - 2) and tile width of a slab variant.
 int slab_rows(int variant);
 int slab_width(int variant);

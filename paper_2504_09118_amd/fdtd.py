@@ -92,6 +92,18 @@ class _PoolCounters(ctypes.Structure):
     ]
 
 
+class _AdjProblem(ctypes.Structure):
+    _fields_ = [
+        ("src_field", ctypes.c_int),
+        ("src_i", ctypes.c_int), ("src_j", ctypes.c_int), ("src_k", ctypes.c_int),
+        ("waveform", ctypes.c_void_p),
+        ("nprobes", ctypes.c_int),
+        ("probes", ctypes.c_void_p),
+        ("nsteps", ctypes.c_longlong),
+        ("checkpoint_every", ctypes.c_int),
+    ]
+
+
 _lib = None
 
 
@@ -102,6 +114,13 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libfdtd.so not found at {LIB_PATH}; build it with __graft_entry__.build()")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same soname). Loaded
+    # first, it also serves this library; loaded after it, torch would open a second
+    # runtime that finds no device. So bring torch in first when it is installed.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, ll, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_size_t
     p6 = ctypes.c_void_p * 6
@@ -139,6 +158,12 @@ def load_library():
     lib.fdtd_pool_release.argtypes = [vp, ll]
     lib.fdtd_pool_stats.argtypes = [vp, ctypes.POINTER(_PoolCounters)]
     lib.fdtd_pool_destroy.argtypes = [vp]
+    lib.fdtd_adjoint_create.argtypes = [vp, ctypes.POINTER(_AdjProblem), ctypes.POINTER(vp)]
+    lib.fdtd_adjoint_forward.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.fdtd_adjoint_backward.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp, i]
+    lib.fdtd_adjoint_destroy.argtypes = [vp]
+    for name in ("fdtd_adjoint_create", "fdtd_adjoint_forward", "fdtd_adjoint_backward", "fdtd_adjoint_destroy"):
+        getattr(lib, name).restype = i
     for name in ("fdtd_init_random", "fdtd_pool_opts_default", "fdtd_pool_request_bytes", "fdtd_pool_create",
                  "fdtd_pool_submit", "fdtd_pool_wait", "fdtd_pool_info", "fdtd_pool_fetch", "fdtd_pool_release",
                  "fdtd_pool_stats", "fdtd_pool_destroy"):

@@ -1,0 +1,179 @@
+"""GPU adjoint (reverse-time) gradient of the driven-cavity probe objective.
+
+- FP64 storage against the oracle's discrete adjoint (24^3, 100 steps, ragged
+  checkpoint segments): dJ/d eps_r and dJ/dE^0 to 1e-10 relative L2.
+- FP32 storage in parity mode (the oracle gets the FP32-rounded coefficients,
+  initial state and source values): the FP32 bar of the forward path, 1e-5.
+- Checkpoint-and-recompute is exact: any checkpoint interval gives the same bits.
+- The 128^3, 500-step problem against stored central differences of the FP64
+  oracle (16 cells): |g - g_FD| <= 1e-3 max(|g_FD|, 1e-2 max_k |g_FD,k|).
+- torch.autograd: eps_r.grad from J.backward() is the library's gradient, and
+  a directional difference of J (FP64 storage) matches <grad, d>.
+"""
+
+import json
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+import cavity_inputs as ci
+import oracle
+from oracle import adjoint as oadj
+from tests.test_gpu_parity import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+S = 0.5 / math.sqrt(3.0)
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _pkg():
+    import paper_2504_09118_amd as P
+    from paper_2504_09118_amd import adjoint as A
+
+    return P, A
+
+
+def problem24(nsteps=100):
+    n = 24
+    eps = ci.uniform_cell_eps(n, n, n, seed=5, lo=1.0, hi=4.0)
+    src = (2, 12, 12, 12)
+    probes = [(2,) + p for p in ci.distinct_nodes(55, 8, (1, 1, 0), (n, n, n))]
+    wave = ci.gaussian_pulse(nsteps, center=30.0, width=10.0)
+    e0 = ci.random_e(n, n, n, seed=6)
+    return n, eps, src, probes, wave, e0
+
+
+def gpu_gradient(n, eps, src, probes, wave, e0, storage, k_every, lam0=True):
+    P, A = _pkg()
+    with P.Solver(n, n, n, 1.0, S, eps_r=eps, storage=storage) as s:
+        s.set_fields(e0)
+        with A.Adjoint(s, src, wave, probes, len(wave), checkpoint_every=k_every) as a:
+            J = a.forward()
+            out = a.backward(lam0=lam0)
+    return (J,) + (out if lam0 else (out,))
+
+
+def oracle_gradient(n, eps, src, probes, wave, e0, parity32=False):
+    ce = oracle.coef_e(n, n, n, 1.0, S, eps)
+    ch = oracle.coef_h(n, n, n, 1.0, S)
+    if parity32:
+        ce, ch = oracle.round_to(ce, np.float32), oracle.round_to(ch, np.float32)
+        e0 = [np.asarray(a).astype(np.float32).astype(np.float64) for a in e0]
+        wave = np.asarray(wave).astype(np.float32).astype(np.float64)
+    state0 = oracle.make_state(e0)
+    res = oadj.adjoint_driven(state0, ce, ch, len(wave), src, wave, probes)
+    return res["J"], oadj.grad_eps(res["gce"], eps, 1.0, S), res["lam0"]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+def test_adjoint_fp64_matches_oracle_adjoint():
+    n, eps, src, probes, wave, e0 = problem24()
+    J, g, lam0 = gpu_gradient(n, eps, src, probes, wave, e0, "f64", k_every=7)
+    Jr, gr, lr = oracle_gradient(n, eps, src, probes, wave, e0)
+    assert abs(J - Jr) <= 1e-12 * Jr
+    assert rel(g, gr) <= 1e-10
+    assert rel_l2(lam0, lr) <= 1e-10
+
+
+def test_adjoint_fp32_parity():
+    n, eps, src, probes, wave, e0 = problem24()
+    J, g, lam0 = gpu_gradient(n, eps, src, probes, wave, e0, "f32", k_every=50)
+    Jr, gr, lr = oracle_gradient(n, eps, src, probes, wave, e0, parity32=True)
+    assert abs(J - Jr) <= 1e-5 * Jr
+    assert rel(g, gr) <= 1e-5
+    assert rel_l2(lam0, lr) <= 1e-5
+
+
+def test_checkpoint_interval_does_not_change_bits():
+    n, eps, src, probes, wave, e0 = problem24(nsteps=60)
+    ref = gpu_gradient(n, eps, src, probes, wave, e0, "f32", k_every=60)
+    for k in (1, 7, 25):
+        got = gpu_gradient(n, eps, src, probes, wave, e0, "f32", k_every=k)
+        assert got[0] == ref[0]
+        assert np.array_equal(got[1], ref[1])
+        for a, b in zip(got[2], ref[2]):
+            assert np.array_equal(a, b)
+
+
+def test_adjoint_argument_errors():
+    P, A = _pkg()
+    n = 12
+    eps = ci.uniform_cell_eps(n, n, n, seed=1)
+    wave = np.ones(5)
+    with P.Solver(n, n, n, 1.0, S) as s:  # no per-cell eps
+        with pytest.raises(P.FdtdError) as ei:
+            A.Adjoint(s, (2, 5, 5, 5), wave, [(2, 3, 3, 3)], 5)
+        assert ei.value.status == -6
+    with P.Solver(n, n, n, 1.0, S, eps_r=eps) as s:
+        s.set_fields([np.zeros(sh) for sh in P.field_shapes(n, n, n)[:3]])
+        with pytest.raises(P.FdtdError):
+            A.Adjoint(s, (2, 0, 5, 5), wave, [], 5)  # Ez on the x = 0 wall
+        with pytest.raises(P.FdtdError):
+            A.Adjoint(s, (2, 5, 5, 5), wave, [(0, 3, 0, 3)], 5)  # Ex on the y = 0 wall
+        with A.Adjoint(s, (2, 5, 5, 5), wave, [(2, 3, 3, 3)], 5) as a:
+            with pytest.raises(P.FdtdError) as ei:
+                a.backward()
+            assert ei.value.status == -5
+
+
+def test_config_128_gradient_vs_oracle_finite_differences():
+    P, A = _pkg()
+    with open(os.path.join(HERE, "golden", "adjoint_fd_128.json")) as f:
+        gold = json.load(f)
+    n, steps = gold["n"], gold["steps"]
+    eps = ci.uniform_cell_eps(n, n, n, seed=gold["eps_seed"], lo=1.0, hi=4.0)
+    probes = [(2,) + p for p in ci.distinct_nodes(gold["probe_seed"], 8, (1, 1, 0), (n, n, n))]
+    cells = ci.distinct_nodes(gold["cell_seed"], 16, (0, 0, 0), (n, n, n))
+    assert [list(p) for p in probes] == gold["probes"] and [list(c) for c in cells] == gold["cells"]
+    wave = ci.gaussian_pulse(steps, center=gold["pulse_center"], width=gold["pulse_width"])
+    import torch
+
+    stream = torch.cuda.Stream()
+    with P.Solver(n, n, n, 1.0, S, eps_r=eps, stream=stream) as s:
+        s.set_fields([np.zeros(sh) for sh in P.field_shapes(n, n, n)[:3]])
+        with A.Adjoint(s, tuple(gold["source"]), wave, probes, steps, checkpoint_every=50) as a:
+            t0 = time.perf_counter()
+            J = a.forward()
+            t1 = time.perf_counter()
+            g = a.backward()
+            t2 = time.perf_counter()
+    print(f"\n128^3 x {steps}: forward {1e3 * (t1 - t0):.1f} ms, backward {1e3 * (t2 - t1):.1f} ms, "
+          f"J = {J:.9e} (oracle {gold['J']:.9e})")
+    assert abs(J - gold["J"]) <= 1e-5 * gold["J"]
+    fd = np.array(gold["fd"])
+    got = np.array([g[k, j, i] for (i, j, k) in cells])
+    floor = 1e-2 * np.abs(fd).max()
+    err = np.abs(got - fd)
+    bound = 1e-3 * np.maximum(np.abs(fd), floor)
+    assert np.all(err <= bound), list(zip(err / np.maximum(np.abs(fd), floor), fd))
+
+
+def test_probe_objective_autograd():
+    import torch
+
+    P, A = _pkg()
+    n, eps, src, probes, wave, e0 = problem24(nsteps=40)
+    eps_t = torch.tensor(eps, device="cuda", requires_grad=True)
+    prob = dict(nsteps=len(wave), src=src, wave=wave, probes=probes, dt=S, e0=e0, checkpoint_every=9,
+                storage="f64")
+    J = A.probe_objective(eps_t, **prob)
+    J.backward()
+    g = eps_t.grad.detach().cpu().numpy()
+    _, gref, _ = gpu_gradient(n, eps, src, probes, wave, e0, "f64", k_every=9)
+    assert np.array_equal(g, gref)
+    # directional difference of J in FP64 storage
+    d = ci.uniform_cell_eps(n, n, n, seed=77, lo=-1.0, hi=1.0)
+    t = 1e-4
+    with torch.no_grad():
+        jp = A.probe_objective(torch.tensor(eps + t * d, device="cuda"), **prob).item()
+        jm = A.probe_objective(torch.tensor(eps - t * d, device="cuda"), **prob).item()
+    fd = (jp - jm) / (2 * t)
+    dot = float(np.sum(g * d))
+    assert abs(fd - dot) <= 1e-6 * abs(dot)
