@@ -81,6 +81,7 @@ def main() -> int:
                     help="device field storage (16-bit fields compute in FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--autotune", action="store_true", help="time every built schedule first and keep the fastest")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-load", type=float, default=0.9, help="offered load, fraction of saturation")
@@ -111,6 +112,11 @@ def main() -> int:
     s = Solver(nx, ny, nz, dx, dt, eps_r=eps, kernel=args.kernel, tb_steps=args.tb_steps, storage=args.storage,
                stream=stream)
     s.set_fields(e)
+    tuned = None
+    if args.autotune:
+        chosen, tried = s.autotune()
+        tuned = {"chosen": chosen, "tried": len(tried)}
+        print(f"[bench] autotune: {chosen} of {len(tried)}", file=sys.stderr, flush=True)
     q = s.query()
     kernel = q["kernel"]
     steps_per_launch = int(q["steps_per_sweep"])
@@ -131,6 +137,7 @@ def main() -> int:
     wall = time.perf_counter() - w0
     ms = ev0.elapsed_time(ev1)
     sweeps = s.query()["sweeps"] - sweeps_before
+    s_sched = s.schedule
     d = s.diag()
     s.close()
 
@@ -167,6 +174,7 @@ def main() -> int:
         "config": {"workload": f"box cavity {nx}x{ny}x{nz}, {STORAGE_LABEL[args.storage]} fields, per-node Ce from per-cell eps_r, "
                                f"scalar Ch, Courant 0.5/sqrt(3)",
                    "kernel": kernel, "steps_per_launch": steps_per_launch, "field_storage": args.storage,
+                   "schedule": {k: v for k, v in s_sched.items() if k != "ms_per_step"}, "autotuned": tuned is not None,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

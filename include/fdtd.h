@@ -204,6 +204,38 @@ int fdtd_diag(fdtd_t h, double out[FDTD_DIAG_N]);
  */
 int fdtd_query(fdtd_t h, long long out[8]);
 
+/*
+ * Schedule of fdtd_step: which kernel, its steps per sweep, tile shape and
+ * z-split. Every schedule gives the same bits for the same storage type, so
+ * choosing one changes only speed.
+ */
+typedef struct {
+    int kernel;         /* FDTD_KERNEL_PLAIN .. FDTD_KERNEL_TEMPORAL */
+    int tb_steps;       /* steps per sweep (temporal: 1..3; others 1) */
+    int variant;        /* tile shape: slab 0..3 = (cells per lane, waves) (2,16) (2,8) (1,16) (1,8);
+                           temporal 0..1 = 64 columns x 2 rows per wave, 128 columns x 1 row per wave */
+    int zchunks;        /* z-ranges per launch (fused, slab, temporal), 1..nz */
+    double ms_per_step; /* fdtd_autotune results: measured milliseconds per leapfrog step */
+} fdtd_schedule;
+
+/* The schedule fdtd_step uses now. */
+int fdtd_get_schedule(fdtd_t h, fdtd_schedule *out);
+
+/* Use this schedule from now on (FDTD_E_ARG / FDTD_E_UNSUPPORTED for a combination not built). */
+int fdtd_set_schedule(fdtd_t h, const fdtd_schedule *sched);
+
+/*
+ * Time every built schedule on this solver (its grid, storage and
+ * coefficients: tile sizes, steps per sweep and z-split; the search the
+ * paper leaves as future work, Sec. 7) for trial_steps steps each (0: 6;
+ * rounded up to whole sweeps) after one warm-up sweep, and keep the fastest.
+ * The state and the step count are restored afterwards (a copy of the six
+ * field boxes is held in a temporary device allocation during the call).
+ * results (may be NULL) receives up to max_results schedules in the order
+ * tried, each with ms_per_step; *n_results (may be NULL) the number tried.
+ */
+int fdtd_autotune(fdtd_t h, int trial_steps, fdtd_schedule *results, int max_results, int *n_results);
+
 /* The hipStream_t the solver enqueues on. */
 void *fdtd_stream(fdtd_t h);
 

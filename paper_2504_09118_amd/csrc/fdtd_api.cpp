@@ -10,6 +10,7 @@
 //   diag: FP64 partial sums of the diagnostics
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -19,6 +20,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_set>
+#include <vector>
 
 #include "fdtd.h"
 #include "fdtd_internal.h"
@@ -814,6 +816,199 @@ int fdtd_destroy(fdtd_t h)
     delete h;
     if (e != hipSuccess)
         return fail(FDTD_E_DEVICE, "destroy: pending work failed: %s", hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+int fdtd_get_schedule(fdtd_t h, fdtd_schedule *out)
+{
+    if (!is_live(h) || h->magic != kMagic)
+        return fail(FDTD_E_STATE, "invalid or destroyed solver handle");
+    if (!out)
+        return fail(FDTD_E_ARG, "NULL out");
+    memset(out, 0, sizeof *out);
+    out->kernel = h->kernel;
+    out->tb_steps = h->kernel == FDTD_KERNEL_TEMPORAL ? h->tb : 1;
+    out->variant = h->kernel == FDTD_KERNEL_TEMPORAL ? h->tvariant
+                   : h->kernel == FDTD_KERNEL_SLAB   ? (h->storage == FDTD_F64 ? 3 : h->variant)
+                                                     : 0;
+    out->zchunks = h->kernel == FDTD_KERNEL_TEMPORAL ? h->tzchunk : h->kernel == FDTD_KERNEL_PLAIN ? 1 : h->zchunk;
+    return FDTD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int validate_schedule(fdtd_t h, const fdtd_schedule *sc)
+{
+    if (sc->kernel < FDTD_KERNEL_PLAIN || sc->kernel > FDTD_KERNEL_TEMPORAL)
+        return fail(FDTD_E_ARG, "unknown kernel %d", sc->kernel);
+    if (is16(h->storage) && sc->kernel != FDTD_KERNEL_TEMPORAL)
+        return fail(FDTD_E_UNSUPPORTED, "16-bit storage is built for the temporal kernel only");
+    if (h->storage == FDTD_F64 && sc->kernel == FDTD_KERNEL_TEMPORAL)
+        return fail(FDTD_E_UNSUPPORTED, "the temporal kernel is not built for FP64 storage");
+    if (sc->kernel == FDTD_KERNEL_TEMPORAL && (sc->tb_steps < 1 || sc->tb_steps > 3))
+        return fail(FDTD_E_ARG, "tb_steps must be 1..3, got %d", sc->tb_steps);
+    if (sc->kernel == FDTD_KERNEL_TEMPORAL && (sc->variant < 0 || sc->variant > 1))
+        return fail(FDTD_E_ARG, "temporal variant must be 0..1, got %d", sc->variant);
+    if (sc->kernel == FDTD_KERNEL_SLAB && (sc->variant < 0 || sc->variant > 3))
+        return fail(FDTD_E_ARG, "slab variant must be 0..3, got %d", sc->variant);
+    if (sc->kernel == FDTD_KERNEL_SLAB && h->storage == FDTD_F64 && sc->variant != 3)
+        return fail(FDTD_E_UNSUPPORTED, "FP64 storage builds slab variant 3 only");
+    if (sc->kernel != FDTD_KERNEL_PLAIN && (sc->zchunks < 1 || sc->zchunks > h->nz))
+        return fail(FDTD_E_ARG, "zchunks must be 1..nz, got %d", sc->zchunks);
+    return FDTD_OK;
+}
+
+void apply_schedule(fdtd_t h, const fdtd_schedule *sc)
+{
+    h->kernel = sc->kernel;
+    if (sc->kernel == FDTD_KERNEL_TEMPORAL) {
+        h->tb = sc->tb_steps;
+        h->tvariant = sc->variant;
+        h->tzchunk = sc->zchunks;
+    } else {
+        h->tb = 1;
+        if (sc->kernel == FDTD_KERNEL_SLAB)
+            h->variant = sc->variant;
+        if (sc->kernel != FDTD_KERNEL_PLAIN)
+            h->zchunk = sc->zchunks;
+    }
+}
+
+std::vector<fdtd_schedule> schedule_candidates(fdtd_t h)
+{
+    std::vector<fdtd_schedule> out;
+    std::vector<int> zcs;
+    for (int zc = 1; zc <= 16; zc *= 2)
+        if (zc == 1 || h->nz / zc >= 16)
+            zcs.push_back(zc);
+    auto add = [&](int kernel, int tb, int variant, int zc) {
+        fdtd_schedule sc{};
+        sc.kernel = kernel;
+        sc.tb_steps = tb;
+        sc.variant = variant;
+        sc.zchunks = zc;
+        out.push_back(sc);
+    };
+    if (!is16(h->storage)) {
+        add(FDTD_KERNEL_PLAIN, 1, 0, 1);
+        for (int zc : zcs) add(FDTD_KERNEL_FUSED, 1, 0, zc);
+        for (int v = 0; v < 4; ++v) {
+            if (h->storage == FDTD_F64 && v != 3)
+                continue;
+            for (int zc : zcs) add(FDTD_KERNEL_SLAB, 1, v, zc);
+        }
+    }
+    if (h->storage != FDTD_F64)
+        for (int tb = 1; tb <= 3; ++tb)
+            for (int v = 0; v < 2; ++v)
+                for (int zc : zcs) add(FDTD_KERNEL_TEMPORAL, tb, v, zc);
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdtd_set_schedule(fdtd_t h, const fdtd_schedule *sc)
+{
+    if (int st = check(h))
+        return st;
+    if (!sc)
+        return fail(FDTD_E_ARG, "NULL schedule");
+    if (int st = validate_schedule(h, sc))
+        return st;
+    apply_schedule(h, sc);
+    return FDTD_OK;
+}
+
+int fdtd_autotune(fdtd_t h, int trial_steps, fdtd_schedule *results, int max_results, int *n_results)
+{
+    if (int st = check(h))
+        return st;
+    if (trial_steps < 0 || max_results < 0 || (max_results > 0 && !results))
+        return fail(FDTD_E_ARG, "bad autotune arguments");
+    const int steps = trial_steps ? trial_steps : 6;
+    if (int st = use_device(h))
+        return st;
+    const std::vector<fdtd_schedule> cands = schedule_candidates(h);
+    // keep the state: copy the current buffer's six boxes aside
+    void *backup = nullptr;
+    const size_t fbox = h->plan.fbox_bytes, guard = (size_t)fdtd::kGuardElems * h->plan.fesz;
+    hipError_t e = hipMalloc(&backup, 6 * fbox);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(FDTD_E_NOMEM, "autotune needs %zu bytes of scratch: %s", 6 * fbox, hipGetErrorString(e));
+    }
+    const int cur0 = h->cur;
+    const long long steps0 = h->steps, sweeps0 = h->sweeps;
+    fdtd_schedule keep;
+    fdtd_get_schedule(h, &keep);
+    for (int q = 0; q < 6 && e == hipSuccess; ++q)
+        e = hipMemcpyAsync((char *)backup + q * fbox, (char *)h->fld[cur0][q] - guard, fbox, hipMemcpyDeviceToDevice,
+                           h->stream);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (e == hipSuccess)
+        e = hipEventCreate(&ev0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&ev1);
+    int best = -1;
+    double best_ms = 0;
+    std::vector<double> times(cands.size(), 0.0);
+    for (size_t c = 0; c < cands.size() && e == hipSuccess; ++c) {
+        apply_schedule(h, &cands[c]);
+        const int tb = cands[c].kernel == FDTD_KERNEL_TEMPORAL ? cands[c].tb_steps : 1;
+        const long long n = (steps + tb - 1) / tb * tb;  // whole sweeps
+        int st = by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, tb); });
+        if (st == FDTD_OK && (e = hipEventRecord(ev0, h->stream)) == hipSuccess) {
+            st = by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, n); });
+            if (st == FDTD_OK)
+                e = hipEventRecord(ev1, h->stream);
+            if (st == FDTD_OK && e == hipSuccess)
+                e = hipEventSynchronize(ev1);
+        }
+        if (st != FDTD_OK) {
+            e = hipErrorLaunchFailure;
+            break;
+        }
+        float ms = 0;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, ev0, ev1);
+        times[c] = (double)ms / (double)n;
+        if (best < 0 || times[c] < best_ms) {
+            best = (int)c;
+            best_ms = times[c];
+        }
+    }
+    // restore the state and counters whatever happened
+    h->cur = cur0;
+    for (int q = 0; q < 6; ++q) {
+        hipError_t e2 = hipMemcpyAsync((char *)h->fld[cur0][q] - guard, (char *)backup + q * fbox, fbox,
+                                       hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess)
+            e = e2;
+    }
+    hipError_t e3 = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess)
+        e = e3;
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    (void)hipFree(backup);
+    h->steps = steps0;
+    h->sweeps = sweeps0;
+    if (e != hipSuccess) {
+        apply_schedule(h, &keep);
+        return device_fail(h, e, "autotune");
+    }
+    apply_schedule(h, &cands[best]);
+    const int nres = std::min<int>(max_results, (int)cands.size());
+    for (int c = 0; c < nres; ++c) {
+        results[c] = cands[c];
+        results[c].ms_per_step = times[c];
+    }
+    if (n_results)
+        *n_results = (int)cands.size();
     return FDTD_OK;
 }
 

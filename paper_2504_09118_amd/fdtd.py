@@ -47,6 +47,16 @@ class _Opts(ctypes.Structure):
     ]
 
 
+class _Schedule(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_int),
+        ("tb_steps", ctypes.c_int),
+        ("variant", ctypes.c_int),
+        ("zchunks", ctypes.c_int),
+        ("ms_per_step", ctypes.c_double),
+    ]
+
+
 class _PoolOpts(ctypes.Structure):
     _fields_ = [
         ("hbm_budget", ctypes.c_size_t),
@@ -158,6 +168,11 @@ def load_library():
     lib.fdtd_pool_release.argtypes = [vp, ll]
     lib.fdtd_pool_stats.argtypes = [vp, ctypes.POINTER(_PoolCounters)]
     lib.fdtd_pool_destroy.argtypes = [vp]
+    lib.fdtd_get_schedule.argtypes = [vp, ctypes.POINTER(_Schedule)]
+    lib.fdtd_set_schedule.argtypes = [vp, ctypes.POINTER(_Schedule)]
+    lib.fdtd_autotune.argtypes = [vp, i, ctypes.POINTER(_Schedule), i, ctypes.POINTER(i)]
+    for name in ("fdtd_get_schedule", "fdtd_set_schedule", "fdtd_autotune"):
+        getattr(lib, name).restype = i
     lib.fdtd_adjoint_create.argtypes = [vp, ctypes.POINTER(_AdjProblem), ctypes.POINTER(vp)]
     lib.fdtd_adjoint_forward.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.fdtd_adjoint_backward.argtypes = [vp, ctypes.POINTER(ctypes.c_double), vp, i]
@@ -355,6 +370,32 @@ class Solver:
     @property
     def stream(self) -> int:
         return int(self._lib.fdtd_stream(self._h) or 0)
+
+    # --------------------------------------------------------------- schedule
+    @staticmethod
+    def _sched_dict(sc) -> dict:
+        return {"kernel": KERNEL_NAMES.get(sc.kernel, sc.kernel), "tb_steps": sc.tb_steps, "variant": sc.variant,
+                "zchunks": sc.zchunks, "ms_per_step": sc.ms_per_step}
+
+    @property
+    def schedule(self) -> dict:
+        """The schedule fdtd_step uses: kernel, tb_steps, variant (tile shape), zchunks."""
+        sc = _Schedule()
+        _check(self._lib.fdtd_get_schedule(self._h, ctypes.byref(sc)))
+        return self._sched_dict(sc)
+
+    def set_schedule(self, kernel, tb_steps=1, variant=0, zchunks=1) -> None:
+        sc = _Schedule(kernel=KERNELS[kernel] if isinstance(kernel, str) else int(kernel), tb_steps=int(tb_steps),
+                       variant=int(variant), zchunks=int(zchunks))
+        _check(self._lib.fdtd_set_schedule(self._h, ctypes.byref(sc)))
+
+    def autotune(self, trial_steps: int = 6):
+        """Time every built schedule here, keep the fastest; returns (chosen, all tried)."""
+        cap = 256
+        res = (_Schedule * cap)()
+        n = ctypes.c_int(0)
+        _check(self._lib.fdtd_autotune(self._h, int(trial_steps), res, cap, ctypes.byref(n)))
+        return self.schedule, [self._sched_dict(res[i]) for i in range(min(n.value, cap))]
 
     def close(self) -> None:
         if self._h:

@@ -197,3 +197,12 @@ def test_serving_request_distribution():
     ref = ci.splitmix64(4, np.arange(5, dtype=np.uint64))
     assert [s[4] for s in specs[:5]] == [int(x) for x in ref]
     assert abs(serve.mean_work() - 216.0 ** 3 * 1100) < 1
+
+
+def test_schedule_calls_reject_invalid_handles():
+    lib = F.load_library()
+    sc = F._Schedule()
+    n = ctypes.c_int(0)
+    assert lib.fdtd_get_schedule(None, ctypes.byref(sc)) == F.E_STATE
+    assert lib.fdtd_set_schedule(ctypes.c_void_p(0x99), ctypes.byref(sc)) == F.E_STATE
+    assert lib.fdtd_autotune(None, 6, None, 0, ctypes.byref(n)) == F.E_STATE
