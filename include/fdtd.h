@@ -103,7 +103,22 @@ typedef struct {
     void *stream;       /* hipStream_t to enqueue on; NULL: the library creates its own */
     void *arena;        /* caller-owned device memory for all device state; NULL: hipMalloc */
     size_t arena_bytes; /* size of arena in bytes (>= fdtd_required_bytes) */
+    double dy, dz;      /* cell size along y and z; 0: dx (cubic cells). Giving either selects
+                           rectangular cells (see below) */
 } fdtd_opts;
+
+/*
+ * Rectangular cells (dx, dy, dz; the naive curl_Hx listing of Sec. 2.1 keeps
+ * Dy and Dz): each difference of Eq. 2 is divided by its own spacing. The
+ * device stores E_a s_a and H_a s_a with s = (1, dy/dx, dz/dx) (edge
+ * integrals in units of dx), in which variables the update is the cubic one
+ * with component a's coefficient multiplied by s_a / (s_b s_c) (b, c the other
+ * axes); those coefficients are per-node arrays, computed in FP64 like the
+ * cubic ones. set/get calls take and return physical values (the scaling is
+ * applied in FP64 and rounded once); fdtd_get_coefs and fdtd_diag report the
+ * stored variables. Courant limit: dt sqrt(1/dx^2 + 1/dy^2 + 1/dz^2) <
+ * sqrt(min eps_r min mu_r). The adjoint and the serving pool take cubic cells.
+ */
 
 /* Fill *opts with the defaults listed above. Returns FDTD_E_ARG for NULL. */
 int fdtd_opts_default(fdtd_opts *opts);

@@ -51,6 +51,9 @@ def _load():
         lib.yee_update_e.argtypes = [i, i, i] + [_dp] * 9
         lib.yee_pec.argtypes = [i, i, i, _dp, _dp, _dp]
         lib.yee_run.argtypes = [i, i, i] + [_dp] * 12 + [ctypes.c_longlong]
+        lib.yee_update_h_rect.argtypes = [i, i, i] + [_dp] * 9 + [d, d, d]
+        lib.yee_update_e_rect.argtypes = [i, i, i] + [_dp] * 9 + [d, d, d]
+        lib.yee_run_rect.argtypes = [i, i, i] + [_dp] * 12 + [d, d, d, ctypes.c_longlong]
         lib.yee_energy.argtypes = [i, i, i] + [_dp] * 12 + [_dp]
         lib.yee_div_h.argtypes = [i, i, i] + [_dp] * 7
         lib.yee_div_d.argtypes = [i, i, i] + [_dp] * 7
@@ -144,6 +147,32 @@ def run(fields, ce, ch, nsteps: int) -> None:
     _load().yee_run(nx, ny, nz, *map(_p, fields), *map(_p, ce), *map(_p, ch), int(nsteps))
 
 
+def coef_rect(nx, ny, nz, dt, eps=None, mu=None):
+    """(dt/eps per E node, dt/mu per H node) for rectangular cells: no spacing folded in."""
+    return coef_e(nx, ny, nz, 1.0, dt, eps), coef_h(nx, ny, nz, 1.0, dt, mu)
+
+
+def update_h_rect(fields, chm, d) -> None:
+    nx, ny, nz = dims_of(fields)
+    ex, ey, ez, hx, hy, hz = fields
+    _load().yee_update_h_rect(nx, ny, nz, _p(hx), _p(hy), _p(hz), _p(ex), _p(ey), _p(ez), *map(_p, chm),
+                              *map(float, d))
+
+
+def update_e_rect(fields, cem, d) -> None:
+    nx, ny, nz = dims_of(fields)
+    ex, ey, ez, hx, hy, hz = fields
+    _load().yee_update_e_rect(nx, ny, nz, _p(ex), _p(ey), _p(ez), _p(hx), _p(hy), _p(hz), *map(_p, cem),
+                              *map(float, d))
+
+
+def run_rect(fields, cem, chm, d, nsteps: int) -> None:
+    """Advance (E^n, H^{n-1/2}) by nsteps steps on dx x dy x dz cells (d = (dx, dy, dz)), in place."""
+    nx, ny, nz = dims_of(fields)
+    _load().yee_run_rect(nx, ny, nz, *map(_p, fields), *map(_p, cem), *map(_p, chm), *map(float, d),
+                         int(nsteps))
+
+
 def energy(fields, ce, ch):
     """(W, sum E^2, sum H^2); W is the exactly conserved discrete energy."""
     nx, ny, nz = dims_of(fields)
@@ -193,5 +222,5 @@ def make_state(e, h=None):
 __all__ = [
     "coef_e", "coef_h", "round_to", "pec", "update_h", "update_e", "run", "energy", "div_h",
     "div_d", "tangential_max", "make_state", "shapes", "dims_of", "set_threads", "get_threads",
-    "max_threads",
+    "max_threads", "coef_rect", "update_h_rect", "update_e_rect", "run_rect",
 ]

@@ -245,6 +245,90 @@ void yee_run(int nx, int ny, int nz,
 }
 
 /*
+ * Rectangular cells dx x dy x dz: Eq. 2 with each difference divided by its
+ * own spacing, as the naive curl_Hx listing writes with Dy and Dz, in
+ * physical field values. Coefficients are ch = dt/mu and ce = dt/eps with no
+ * spacing folded in (yee_coef_h / yee_coef_e with dx = 1 produce them).
+ */
+void yee_update_h_rect(int nx, int ny, int nz,
+                       double *hx, double *hy, double *hz,
+                       const double *ex, const double *ey, const double *ez,
+                       const double *chx, const double *chy, const double *chz,
+                       double dx, double dy, double dz)
+{
+    const int ExX = nx, ExY = ny + 1;
+    const int EyX = nx + 1, EyY = ny;
+    const int EzX = nx + 1, EzY = ny + 1;
+    int k;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i)
+                AT(hx, nx + 1, ny, i, j, k) += AT(chx, nx + 1, ny, i, j, k) *
+                    ((AT(ey, EyX, EyY, i, j, k + 1) - AT(ey, EyX, EyY, i, j, k)) / dz -
+                     (AT(ez, EzX, EzY, i, j + 1, k) - AT(ez, EzX, EzY, i, j, k)) / dy);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (k = 0; k < nz; ++k)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                AT(hy, nx, ny + 1, i, j, k) += AT(chy, nx, ny + 1, i, j, k) *
+                    ((AT(ez, EzX, EzY, i + 1, j, k) - AT(ez, EzX, EzY, i, j, k)) / dx -
+                     (AT(ex, ExX, ExY, i, j, k + 1) - AT(ex, ExX, ExY, i, j, k)) / dz);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (k = 0; k <= nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                AT(hz, nx, ny, i, j, k) += AT(chz, nx, ny, i, j, k) *
+                    ((AT(ex, ExX, ExY, i, j + 1, k) - AT(ex, ExX, ExY, i, j, k)) / dy -
+                     (AT(ey, EyX, EyY, i + 1, j, k) - AT(ey, EyX, EyY, i, j, k)) / dx);
+}
+
+void yee_update_e_rect(int nx, int ny, int nz,
+                       double *ex, double *ey, double *ez,
+                       const double *hx, const double *hy, const double *hz,
+                       const double *cex, const double *cey, const double *cez,
+                       double dx, double dy, double dz)
+{
+    const int HxX = nx + 1, HxY = ny;
+    const int HyX = nx, HyY = ny + 1;
+    const int HzX = nx, HzY = ny;
+    int k;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (k = 1; k < nz; ++k)
+        for (int j = 1; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                AT(ex, nx, ny + 1, i, j, k) += AT(cex, nx, ny + 1, i, j, k) *
+                    ((AT(hz, HzX, HzY, i, j, k) - AT(hz, HzX, HzY, i, j - 1, k)) / dy -
+                     (AT(hy, HyX, HyY, i, j, k) - AT(hy, HyX, HyY, i, j, k - 1)) / dz);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (k = 1; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 1; i < nx; ++i)
+                AT(ey, nx + 1, ny, i, j, k) += AT(cey, nx + 1, ny, i, j, k) *
+                    ((AT(hx, HxX, HxY, i, j, k) - AT(hx, HxX, HxY, i, j, k - 1)) / dz -
+                     (AT(hz, HzX, HzY, i, j, k) - AT(hz, HzX, HzY, i - 1, j, k)) / dx);
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+    for (k = 0; k < nz; ++k)
+        for (int j = 1; j < ny; ++j)
+            for (int i = 1; i < nx; ++i)
+                AT(ez, nx + 1, ny + 1, i, j, k) += AT(cez, nx + 1, ny + 1, i, j, k) *
+                    ((AT(hy, HyX, HyY, i, j, k) - AT(hy, HyX, HyY, i - 1, j, k)) / dx -
+                     (AT(hx, HxX, HxY, i, j, k) - AT(hx, HxX, HxY, i, j - 1, k)) / dy);
+}
+
+void yee_run_rect(int nx, int ny, int nz,
+                  double *ex, double *ey, double *ez, double *hx, double *hy, double *hz,
+                  const double *cex, const double *cey, const double *cez,
+                  const double *chx, const double *chy, const double *chz,
+                  double dx, double dy, double dz, long long nsteps)
+{
+    for (long long s = 0; s < nsteps; ++s) {
+        yee_update_h_rect(nx, ny, nz, hx, hy, hz, ex, ey, ez, chx, chy, chz, dx, dy, dz);
+        yee_update_e_rect(nx, ny, nz, ex, ey, ez, hx, hy, hz, cex, cey, cez, dx, dy, dz);
+    }
+}
+
+/*
  * Discrete energy W^n = sum E^2/Ce + sum H^{n-1/2} . H^{n+1/2} / Ch over nodes
  * with a nonzero coefficient. The leapfrog conserves it exactly in exact
  * arithmetic because the E curl is minus the transpose of the H curl.

@@ -255,6 +255,8 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
         return afail(FDTD_E_UNSUPPORTED, "the adjoint is built for FP32 and FP64 storage");
     if (!s->ce_arr)
         return afail(FDTD_E_UNSUPPORTED, "the permittivity gradient needs a solver created with per-cell eps_r");
+    if (s->aniso)
+        return afail(FDTD_E_UNSUPPORTED, "the adjoint is built for cubic cells");
     if (p->nsteps < 1)
         return afail(FDTD_E_ARG, "nsteps must be >= 1 (got %lld)", p->nsteps);
     const int K = p->checkpoint_every ? p->checkpoint_every : 50;

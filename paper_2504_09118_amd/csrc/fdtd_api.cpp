@@ -304,7 +304,8 @@ hipError_t pack_all(fdtd_t h, const void *const src[6], bool staged)
                 return e;
             p = (const S *)h->staging;
         }
-        hipError_t e = fdtd::launch_pack<S, T>(h->plan.g, f, p, (T *)h->fld[0][f], (T *)h->fld[1][f], h->stream);
+        hipError_t e = fdtd::launch_pack<S, T>(h->plan.g, f, p, (T *)h->fld[0][f], (T *)h->fld[1][f], h->stream,
+                                               h->scale[f % 3]);
         if (e != hipSuccess)
             return e;
     }
@@ -312,7 +313,7 @@ hipError_t pack_all(fdtd_t h, const void *const src[6], bool staged)
 }
 
 template <typename T, typename S>
-hipError_t unpack_all(fdtd_t h, void *const dst[6], bool staged, void *const *boxes)
+hipError_t unpack_all(fdtd_t h, void *const dst[6], bool staged, void *const *boxes, bool scaled)
 {
     for (int f = 0; f < 6; ++f) {
         int X, Y, Z;
@@ -324,7 +325,8 @@ hipError_t unpack_all(fdtd_t h, void *const dst[6], bool staged, void *const *bo
             if (e != hipSuccess)
                 return e;
         } else {
-            hipError_t e = fdtd::launch_unpack<T, S>(h->plan.g, f, (const T *)boxes[f], out, h->stream);
+            hipError_t e = fdtd::launch_unpack<T, S>(h->plan.g, f, (const T *)boxes[f], out, h->stream,
+                                                     scaled ? h->scale[f % 3] : 1.0);
             if (e != hipSuccess)
                 return e;
         }
@@ -386,8 +388,8 @@ int get_common(fdtd_t h, void *const dst[6], int dtype, bool staged, void *const
     const int st_box = coefs ? (h->storage == FDTD_F64 ? FDTD_F64 : FDTD_F32) : h->storage;
     hipError_t e = by_storage(st_box, [&](auto tag) {
         using T = decltype(tag);
-        return dtype == FDTD_F32 ? unpack_all<T, float>(h, dst, staged, boxes)
-                                 : unpack_all<T, double>(h, dst, staged, boxes);
+        return dtype == FDTD_F32 ? unpack_all<T, float>(h, dst, staged, boxes, !coefs)
+                                 : unpack_all<T, double>(h, dst, staged, boxes, !coefs);
     });
     if (e != hipSuccess)
         return device_fail(h, e, "get_fields");
@@ -424,7 +426,8 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
     const fdtd_opts *o = opts ? opts : &d;
     if (o->storage < FDTD_F64 || o->storage > FDTD_BF16)
         return fail(FDTD_E_UNSUPPORTED, "storage dtype %d not built", o->storage);
-    Plan p = make_plan(nx, ny, nz, o->storage, coef && coef->eps_r, coef && coef->mu_r);
+    const bool rect = (o->dy > 0.0 || o->dz > 0.0);  // rectangular cells keep per-node coefficient arrays
+    Plan p = make_plan(nx, ny, nz, o->storage, (coef && coef->eps_r) || rect, (coef && coef->mu_r) || rect);
     *out = p.total + 256;  // room to align an arbitrary arena base
     return FDTD_OK;
 }
@@ -456,6 +459,12 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         return fail(FDTD_E_ARG, "tb_steps must be 1..3 (0: default 3), got %d", o->tb_steps);
     if (o->arena && o->arena_bytes == 0)
         return fail(FDTD_E_ARG, "arena given with arena_bytes = 0");
+    if (!(o->dy == 0.0 || finite_pos(o->dy)) || !(o->dz == 0.0 || finite_pos(o->dz)))
+        return fail(FDTD_E_ARG, "dy and dz must be 0 (= dx) or finite and > 0 (got %g, %g)", o->dy, o->dz);
+    const double dy = o->dy > 0.0 ? o->dy : dx, dz = o->dz > 0.0 ? o->dz : dx;
+    // rectangular cells (any spacing given explicitly): per-node coefficient arrays carry the
+    // axis factors; a spacing equal to dx gives factor 1 and the cubic bits
+    const bool rect = o->dy > 0.0 || o->dz > 0.0;
     const double *eps = coef ? coef->eps_r : nullptr;
     const double *mu = coef ? coef->mu_r : nullptr;
     const size_t ncell = (size_t)nx * ny * nz;
@@ -465,13 +474,15 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         return st;
     if ((st = scan_material(mu, ncell, &mu_min, "mu_r")))
         return st;
-    // Courant limit of the cubic Yee grid: c_max dt sqrt(3) / dx < 1, c_max = 1/sqrt(min eps min mu)
-    const double courant = dt * std::sqrt(3.0) / dx;
+    // Courant limit of the Yee grid: c_max dt sqrt(1/dx^2 + 1/dy^2 + 1/dz^2) < 1,
+    // c_max = 1/sqrt(min eps min mu); on cubic cells dt sqrt(3) / dx
+    const double courant =
+        rect ? dt * std::sqrt(1.0 / (dx * dx) + 1.0 / (dy * dy) + 1.0 / (dz * dz)) : dt * std::sqrt(3.0) / dx;
     if (!(courant < std::sqrt(eps_min * mu_min)))
-        return fail(FDTD_E_CFL, "dt*sqrt(3)/dx = %.17g violates the Courant limit %.17g", courant,
+        return fail(FDTD_E_CFL, "dt*sqrt(sum 1/d^2) = %.17g violates the Courant limit %.17g", courant,
                     std::sqrt(eps_min * mu_min));
 
-    Plan p = make_plan(nx, ny, nz, o->storage, eps != nullptr, mu != nullptr);
+    Plan p = make_plan(nx, ny, nz, o->storage, eps != nullptr || rect, mu != nullptr || rect);
     hipError_t e = hipSetDevice(o->device);
     if (e != hipSuccess)
         return fail(FDTD_E_DEVICE, "hipSetDevice(%d): %s", o->device, hipGetErrorString(e));
@@ -483,6 +494,13 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     h->nz = nz;
     h->dx = dx;
     h->dt = dt;
+    h->d[0] = dx;
+    h->d[1] = dy;
+    h->d[2] = dz;
+    h->scale[0] = 1.0;
+    h->scale[1] = dy / dx;
+    h->scale[2] = dz / dx;
+    h->aniso = dy != dx || dz != dx;
     h->storage = o->storage;
     h->kernel = kern;
     h->tb = kern == FDTD_KERNEL_TEMPORAL ? (o->tb_steps > 0 ? o->tb_steps : 3) : 1;
@@ -490,8 +508,8 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     h->zchunk = env_int("FDTD_ZCHUNKS", 0);
     h->variant = env_int("FDTD_SLAB_VARIANT", 0);
     h->plan = p;
-    h->ce_arr = eps != nullptr;
-    h->ch_arr = mu != nullptr;
+    h->ce_arr = eps != nullptr || rect;
+    h->ch_arr = mu != nullptr || rect;
     h->ce_s = dt / dx;
     h->ch_s = dt / dx;
     if (h->zchunk <= 0) {
@@ -574,24 +592,31 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     h->diag = (double *)(base + p.off_diag);
 
     e = hipMemsetAsync(base, 0, p.total, h->stream);
-    // materials -> staging -> FP64 coefficient kernel, one material at a time
+    // materials -> staging -> FP64 coefficient kernel, one material at a time. Rectangular
+    // cells, in the stored variables E_a s_a, H_a s_a (s = 1, dy/dx, dz/dx), update like
+    // cubic cells of size dx with component a's coefficient times s_a / (s_b s_c).
+    const double *sc = h->scale;
+    const double fac[6] = {sc[0] / (sc[1] * sc[2]), sc[1] / (sc[0] * sc[2]), sc[2] / (sc[0] * sc[1]),
+                           sc[0] / (sc[1] * sc[2]), sc[1] / (sc[0] * sc[2]), sc[2] / (sc[0] * sc[1])};
     for (int which = 0; which < 2 && e == hipSuccess; ++which) {
         const double *m = which == 0 ? eps : mu;
-        if (!m)
+        if (!m && !rect)
             continue;
-        e = hipMemcpyAsync(h->staging, m, ncell * sizeof(double), hipMemcpyHostToDevice, h->stream);
+        if (m)
+            e = hipMemcpyAsync(h->staging, m, ncell * sizeof(double), hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess)
             break;
+        const double *md = m ? (const double *)h->staging : nullptr;
         if (h->storage != FDTD_F64) {
             float *ce[3] = {nullptr, nullptr, nullptr}, *ch[3] = {nullptr, nullptr, nullptr};
             for (int f = 0; f < 3; ++f) (which == 0 ? ce : ch)[f] = (float *)(which == 0 ? h->ce[f] : h->ch[f]);
-            e = fdtd::launch_coef<float>(p.g, dx, dt, which == 0 ? (const double *)h->staging : nullptr,
-                                         which == 1 ? (const double *)h->staging : nullptr, ce, ch, h->stream);
+            e = fdtd::launch_coef<float>(p.g, dx, dt, which == 0 ? md : nullptr, which == 1 ? md : nullptr, ce, ch,
+                                         h->stream, rect ? fac : nullptr);
         } else {
             double *ce[3] = {nullptr, nullptr, nullptr}, *ch[3] = {nullptr, nullptr, nullptr};
             for (int f = 0; f < 3; ++f) (which == 0 ? ce : ch)[f] = (double *)(which == 0 ? h->ce[f] : h->ch[f]);
-            e = fdtd::launch_coef<double>(p.g, dx, dt, which == 0 ? (const double *)h->staging : nullptr,
-                                          which == 1 ? (const double *)h->staging : nullptr, ce, ch, h->stream);
+            e = fdtd::launch_coef<double>(p.g, dx, dt, which == 0 ? md : nullptr, which == 1 ? md : nullptr, ce, ch,
+                                          h->stream, rect ? fac : nullptr);
         }
         if (e == hipSuccess)
             e = hipStreamSynchronize(h->stream);  // staging is reused by the next material
@@ -638,7 +663,7 @@ int fdtd_init_random(fdtd_t h, unsigned long long seed)
             a[f] = (T *)h->fld[0][f];
             b[f] = (T *)h->fld[1][f];
         }
-        return fdtd::launch_init_random<T>(h->plan.g, seed, a, b, h->stream);
+        return fdtd::launch_init_random<T>(h->plan.g, seed, a, b, h->stream, h->scale);
     });
     if (e != hipSuccess)
         return device_fail(h, e, "init_random");

@@ -120,7 +120,8 @@ Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool 
 // Seeded random state (E ~ U[-1,1] from a counter-based SplitMix64, PEC walls,
 // H = 0) written into both state buffers a and b (b may hold nullptrs).
 template <typename T>
-hipError_t launch_init_random(const Geom &g, unsigned long long seed, T *const a[6], T *const b[6], hipStream_t s);
+hipError_t launch_init_random(const Geom &g, unsigned long long seed, T *const a[6], T *const b[6], hipStream_t s,
+                              const double *scale = nullptr);
 
 // Driven-cavity adjoint (FP32 / FP64 storage). Point source: add w to node
 // so of component sf (sf < 0: none); probes: record E at (pf, po) into
@@ -147,19 +148,23 @@ int slab_width(int variant);
 
 // FP64 coefficient precompute. eps / mu: device per-cell arrays (nx*ny*nz,
 // x-fastest) or nullptr for 1. Writes the three boxes of each kind that are
-// non-null; dt_dx = dt / dx.
+// non-null: dt / (dx * mean) times fac[f] (fac: six per-component factors of
+// rectangular cells, Ex Ey Ez Hx Hy Hz; nullptr for cubic cells).
 template <typename T>
 hipError_t launch_coef(const Geom &g, double dx, double dt, const double *eps, const double *mu,
-                       T *ce[3], T *ch[3], hipStream_t s);
+                       T *ce[3], T *ch[3], hipStream_t s, const double *fac = nullptr);
 
-// Dense staggered buffer (type S) -> padded box (type T) for field f; writes
-// both destinations (dst2 may be null). E fields get 0 on wall-tangential nodes.
+// Dense staggered buffer (type S) -> padded box (type T) for field f, each
+// value multiplied by scale in FP64 and rounded once; writes both destinations
+// (dst2 may be null). E fields get 0 on wall-tangential nodes.
 template <typename S, typename T>
-hipError_t launch_pack(const Geom &g, int field, const S *src, T *dst, T *dst2, hipStream_t s);
+hipError_t launch_pack(const Geom &g, int field, const S *src, T *dst, T *dst2, hipStream_t s,
+                       double scale = 1.0);
 
-// Padded box (type T) -> dense staggered buffer (type S) for field f.
+// Padded box (type T) -> dense staggered buffer (type S) for field f, each value
+// divided by scale in FP64.
 template <typename T, typename S>
-hipError_t launch_unpack(const Geom &g, int field, const T *src, S *dst, hipStream_t s);
+hipError_t launch_unpack(const Geom &g, int field, const T *src, S *dst, hipStream_t s, double scale = 1.0);
 
 // Diagnostics (FP64). partial must hold diag_partial_doubles() doubles.
 size_t diag_partial_doubles();

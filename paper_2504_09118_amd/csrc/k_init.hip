@@ -26,7 +26,7 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long z)
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_init_random(Geom g, int field, int X, int Y, long long n,
-                                                        unsigned long long seed, T *dst, T *dst2)
+                                                        unsigned long long seed, T *dst, T *dst2, double scale)
 {
     const long long l = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (l >= n)
@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(kBlock) k_init_random(Geom g, int field, int X
             const unsigned long long c = ((unsigned long long)field << 40) + (unsigned long long)l;
             const unsigned long long z = mix64(seed + (c + 1ull) * 0x9E3779B97F4A7C15ull);
             const double u = (double)(z >> 11) * 0x1.0p-53;
-            v = Store<T>::narrow(to_compute<T>(2.0 * u - 1.0));
+            v = Store<T>::narrow(to_compute<T>((2.0 * u - 1.0) * scale));  // exact for scale 1
         }
     }
     const long long o = g.at(i, j, k);
@@ -60,14 +60,15 @@ __global__ void __launch_bounds__(kBlock) k_init_random(Geom g, int field, int X
 }  // namespace
 
 template <typename T>
-hipError_t launch_init_random(const Geom &g, unsigned long long seed, T *const a[6], T *const b[6], hipStream_t s)
+hipError_t launch_init_random(const Geom &g, unsigned long long seed, T *const a[6], T *const b[6], hipStream_t s,
+                              const double *scale)
 {
     for (int f = 0; f < 6; ++f) {
         int X, Y, Z;
         extents(g, f, X, Y, Z);
         const long long n = (long long)X * Y * Z;
         hipLaunchKernelGGL((k_init_random<T>), dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, g,
-                           f, X, Y, n, seed, a[f], b[f]);
+                           f, X, Y, n, seed, a[f], b[f], scale ? scale[f % 3] : 1.0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -76,12 +77,12 @@ hipError_t launch_init_random(const Geom &g, unsigned long long seed, T *const a
 }
 
 template hipError_t launch_init_random<float>(const Geom &, unsigned long long, float *const[6], float *const[6],
-                                              hipStream_t);
+                                              hipStream_t, const double *);
 template hipError_t launch_init_random<double>(const Geom &, unsigned long long, double *const[6],
-                                               double *const[6], hipStream_t);
+                                               double *const[6], hipStream_t, const double *);
 template hipError_t launch_init_random<f16>(const Geom &, unsigned long long, f16 *const[6], f16 *const[6],
-                                            hipStream_t);
+                                            hipStream_t, const double *);
 template hipError_t launch_init_random<bf16>(const Geom &, unsigned long long, bf16 *const[6], bf16 *const[6],
-                                             hipStream_t);
+                                             hipStream_t, const double *);
 
 }  // namespace fdtd

@@ -34,15 +34,15 @@ __device__ __forceinline__ bool e_wall(int field, int i, int j, int k, int nx, i
 
 template <typename S, typename T>
 __global__ void __launch_bounds__(kBlock) k_pack(Geom g, int field, int X, int Y, long long n,
-                                                 const S *__restrict__ src, T *dst, T *dst2)
+                                                 const S *__restrict__ src, T *dst, T *dst2, double scale)
 {
     long long l = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (l >= n)
         return;
     int i, j, k;
     unflatten(l, X, Y, i, j, k);
-    // 16-bit storage: the host value is rounded to FP32, then to the 16-bit type
-    T v = Store<T>::narrow(to_compute<T>(src[l]));
+    // scaled in FP64 (exact for scale 1); 16-bit storage: rounded to FP32, then to the 16-bit type
+    T v = Store<T>::narrow(to_compute<T>((double)src[l] * scale));
     if (e_wall(field, i, j, k, g.nx, g.ny, g.nz))
         v = Store<T>::narrow(0);
     long long o = g.at(i, j, k);
@@ -53,14 +53,14 @@ __global__ void __launch_bounds__(kBlock) k_pack(Geom g, int field, int X, int Y
 
 template <typename T, typename S>
 __global__ void __launch_bounds__(kBlock) k_unpack(Geom g, int X, int Y, long long n,
-                                                   const T *__restrict__ src, S *__restrict__ dst)
+                                                   const T *__restrict__ src, S *__restrict__ dst, double scale)
 {
     long long l = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (l >= n)
         return;
     int i, j, k;
     unflatten(l, X, Y, i, j, k);
-    dst[l] = (S)Store<T>::widen(src[g.at(i, j, k)]);
+    dst[l] = (S)((double)Store<T>::widen(src[g.at(i, j, k)]) / scale);
 }
 
 __device__ __forceinline__ double mat(const double *m, int nx, int ny, int i, int j, int k)
@@ -71,7 +71,7 @@ __device__ __forceinline__ double mat(const double *m, int nx, int ny, int i, in
 // One thread per node of component `field` (0..2 E edges, 3..5 H faces).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coef(Geom g, int field, int X, int Y, long long n, double dx,
-                                                 double dt, const double *__restrict__ m, T *out)
+                                                 double dt, const double *__restrict__ m, T *out, double fac)
 {
     long long l = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (l >= n)
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(kBlock) k_coef(Geom g, int field, int X, int Y
             c = dt / (dx * ((mat(m, nx, ny, i, j, k - 1) + mat(m, nx, ny, i, j, k)) * 0.5));
         break;
     }
-    out[g.at(i, j, k)] = (T)c;  // one rounding, to nearest even
+    out[g.at(i, j, k)] = (T)(c * fac);  // exact for fac 1; one rounding, to nearest even
 }
 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -123,29 +123,29 @@ inline unsigned blocks_for(long long n) { return (unsigned)((n + kBlock - 1) / k
 }  // namespace
 
 template <typename S, typename T>
-hipError_t launch_pack(const Geom &g, int field, const S *src, T *dst, T *dst2, hipStream_t s)
+hipError_t launch_pack(const Geom &g, int field, const S *src, T *dst, T *dst2, hipStream_t s, double scale)
 {
     int X, Y, Z;
     extents(g, field, X, Y, Z);
     long long n = (long long)X * Y * Z;
     hipLaunchKernelGGL((k_pack<S, T>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, field, X, Y, n, src, dst,
-                       dst2);
+                       dst2, scale);
     return hipGetLastError();
 }
 
 template <typename T, typename S>
-hipError_t launch_unpack(const Geom &g, int field, const T *src, S *dst, hipStream_t s)
+hipError_t launch_unpack(const Geom &g, int field, const T *src, S *dst, hipStream_t s, double scale)
 {
     int X, Y, Z;
     extents(g, field, X, Y, Z);
     long long n = (long long)X * Y * Z;
-    hipLaunchKernelGGL((k_unpack<T, S>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, X, Y, n, src, dst);
+    hipLaunchKernelGGL((k_unpack<T, S>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, X, Y, n, src, dst, scale);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_coef(const Geom &g, double dx, double dt, const double *eps, const double *mu, T *ce[3],
-                       T *ch[3], hipStream_t s)
+                       T *ch[3], hipStream_t s, const double *fac)
 {
     for (int f = 0; f < 6; ++f) {
         T *out = f < 3 ? ce[f] : ch[f - 3];
@@ -155,7 +155,7 @@ hipError_t launch_coef(const Geom &g, double dx, double dt, const double *eps, c
         extents(g, f, X, Y, Z);
         long long n = (long long)X * Y * Z;
         hipLaunchKernelGGL((k_coef<T>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, f, X, Y, n, dx, dt,
-                           f < 3 ? eps : mu, out);
+                           f < 3 ? eps : mu, out, fac ? fac[f] : 1.0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -163,26 +163,26 @@ hipError_t launch_coef(const Geom &g, double dx, double dt, const double *eps, c
     return hipSuccess;
 }
 
-template hipError_t launch_pack<float, float>(const Geom &, int, const float *, float *, float *, hipStream_t);
-template hipError_t launch_pack<double, float>(const Geom &, int, const double *, float *, float *, hipStream_t);
-template hipError_t launch_pack<float, double>(const Geom &, int, const float *, double *, double *, hipStream_t);
+template hipError_t launch_pack<float, float>(const Geom &, int, const float *, float *, float *, hipStream_t, double);
+template hipError_t launch_pack<double, float>(const Geom &, int, const double *, float *, float *, hipStream_t, double);
+template hipError_t launch_pack<float, double>(const Geom &, int, const float *, double *, double *, hipStream_t, double);
 template hipError_t launch_pack<double, double>(const Geom &, int, const double *, double *, double *,
-                                                hipStream_t);
-template hipError_t launch_pack<float, f16>(const Geom &, int, const float *, f16 *, f16 *, hipStream_t);
-template hipError_t launch_pack<double, f16>(const Geom &, int, const double *, f16 *, f16 *, hipStream_t);
-template hipError_t launch_pack<float, bf16>(const Geom &, int, const float *, bf16 *, bf16 *, hipStream_t);
-template hipError_t launch_pack<double, bf16>(const Geom &, int, const double *, bf16 *, bf16 *, hipStream_t);
-template hipError_t launch_unpack<f16, float>(const Geom &, int, const f16 *, float *, hipStream_t);
-template hipError_t launch_unpack<f16, double>(const Geom &, int, const f16 *, double *, hipStream_t);
-template hipError_t launch_unpack<bf16, float>(const Geom &, int, const bf16 *, float *, hipStream_t);
-template hipError_t launch_unpack<bf16, double>(const Geom &, int, const bf16 *, double *, hipStream_t);
-template hipError_t launch_unpack<float, float>(const Geom &, int, const float *, float *, hipStream_t);
-template hipError_t launch_unpack<float, double>(const Geom &, int, const float *, double *, hipStream_t);
-template hipError_t launch_unpack<double, float>(const Geom &, int, const double *, float *, hipStream_t);
-template hipError_t launch_unpack<double, double>(const Geom &, int, const double *, double *, hipStream_t);
+                                                hipStream_t, double);
+template hipError_t launch_pack<float, f16>(const Geom &, int, const float *, f16 *, f16 *, hipStream_t, double);
+template hipError_t launch_pack<double, f16>(const Geom &, int, const double *, f16 *, f16 *, hipStream_t, double);
+template hipError_t launch_pack<float, bf16>(const Geom &, int, const float *, bf16 *, bf16 *, hipStream_t, double);
+template hipError_t launch_pack<double, bf16>(const Geom &, int, const double *, bf16 *, bf16 *, hipStream_t, double);
+template hipError_t launch_unpack<f16, float>(const Geom &, int, const f16 *, float *, hipStream_t, double);
+template hipError_t launch_unpack<f16, double>(const Geom &, int, const f16 *, double *, hipStream_t, double);
+template hipError_t launch_unpack<bf16, float>(const Geom &, int, const bf16 *, float *, hipStream_t, double);
+template hipError_t launch_unpack<bf16, double>(const Geom &, int, const bf16 *, double *, hipStream_t, double);
+template hipError_t launch_unpack<float, float>(const Geom &, int, const float *, float *, hipStream_t, double);
+template hipError_t launch_unpack<float, double>(const Geom &, int, const float *, double *, hipStream_t, double);
+template hipError_t launch_unpack<double, float>(const Geom &, int, const double *, float *, hipStream_t, double);
+template hipError_t launch_unpack<double, double>(const Geom &, int, const double *, double *, hipStream_t, double);
 template hipError_t launch_coef<float>(const Geom &, double, double, const double *, const double *, float *[3],
-                                       float *[3], hipStream_t);
+                                       float *[3], hipStream_t, const double *);
 template hipError_t launch_coef<double>(const Geom &, double, double, const double *, const double *,
-                                        double *[3], double *[3], hipStream_t);
+                                        double *[3], double *[3], hipStream_t, const double *);
 
 }  // namespace fdtd

@@ -14,6 +14,9 @@ struct fdtd_solver {
     uint32_t magic;
     int nx, ny, nz;
     double dx, dt;
+    double d[3];      // cell size along x, y, z
+    double scale[3];  // stored component = physical value x scale (1, dy/dx, dz/dx)
+    bool aniso;       // d[1] or d[2] differs from dx
     int storage, kernel, tb, device, zchunk, tzchunk, variant, tvariant;
     hipStream_t stream;
     bool own_stream;

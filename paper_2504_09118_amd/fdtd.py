@@ -44,6 +44,8 @@ class _Opts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("arena", ctypes.c_void_p),
         ("arena_bytes", ctypes.c_size_t),
+        ("dy", ctypes.c_double),
+        ("dz", ctypes.c_double),
     ]
 
 
@@ -221,13 +223,15 @@ def _material_array(m, nx, ny, nz):
     return a
 
 
-def required_bytes(nx, ny, nz, eps_r=None, mu_r=None, storage="f32", kernel="auto"):
+def required_bytes(nx, ny, nz, eps_r=None, mu_r=None, storage="f32", kernel="auto", dy=None, dz=None):
     lib = load_library()
     coef = _Coef(eps_r=1 if eps_r is not None else None, mu_r=1 if mu_r is not None else None)
     opts = _Opts()
     lib.fdtd_opts_default(ctypes.byref(opts))
     opts.storage = STORAGE[storage]
     opts.kernel = KERNELS[kernel]
+    opts.dy = float(dy or 0.0)
+    opts.dz = float(dz or 0.0)
     out = ctypes.c_size_t(0)
     _check(lib.fdtd_required_bytes(nx, ny, nz, ctypes.byref(coef), ctypes.byref(opts), ctypes.byref(out)))
     return out.value
@@ -244,10 +248,11 @@ class Solver:
     torch's current stream; None lets the library create its own stream.
     arena: "torch" to allocate all device state as one torch uint8 tensor
     (kept alive by the solver), or None for the library's own hipMalloc.
+    dy, dz: cell sizes along y and z for rectangular cells (None: dx).
     """
 
     def __init__(self, nx, ny, nz, dx=1.0, dt=None, eps_r=None, mu_r=None, storage="f32", kernel="auto",
-                 tb_steps=0, stream=None, arena=None, device=0):
+                 tb_steps=0, stream=None, arena=None, device=0, dy=None, dz=None):
         self._lib = load_library()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.dx = float(dx)
@@ -266,6 +271,8 @@ class Solver:
         opts.kernel = KERNELS[kernel]
         opts.tb_steps = int(tb_steps)
         opts.device = int(device)
+        opts.dy = float(dy or 0.0)
+        opts.dz = float(dz or 0.0)
         if stream is not None:
             opts.stream = _stream_handle(stream, device)
         if arena == "torch":

@@ -206,3 +206,26 @@ def test_schedule_calls_reject_invalid_handles():
     assert lib.fdtd_get_schedule(None, ctypes.byref(sc)) == F.E_STATE
     assert lib.fdtd_set_schedule(ctypes.c_void_p(0x99), ctypes.byref(sc)) == F.E_STATE
     assert lib.fdtd_autotune(None, 6, None, 0, ctypes.byref(n)) == F.E_STATE
+
+
+def test_rectangular_cells_courant_and_arguments():
+    lib = F.load_library()
+
+    def create(dt, dy, dz):
+        coef = F._Coef()
+        opts = F._Opts()
+        lib.fdtd_opts_default(ctypes.byref(opts))
+        opts.dy, opts.dz = dy, dz
+        h = ctypes.c_void_p(None)
+        st = lib.fdtd_create(8, 8, 8, 1.0, dt, ctypes.byref(coef), ctypes.byref(opts), ctypes.byref(h))
+        if st == F.OK:
+            lib.fdtd_destroy(h)
+        return st
+
+    lim = 1.0 / math.sqrt(1.0 + 1.0 / 0.25 + 1.0 / 4.0)  # dx = 1, dy = 0.5, dz = 2
+    assert create(lim * 1.0000001, 0.5, 2.0) == F.E_CFL
+    assert create(lim * 0.999, 0.5, 2.0) != F.E_CFL
+    assert create(0.1, -1.0, 0.0) == F.E_ARG
+    assert create(0.1, float("nan"), 0.0) == F.E_ARG
+    # rectangular cells always carry per-node coefficient arrays
+    assert F.required_bytes(64, 48, 40, dy=0.5) >= F.required_bytes(64, 48, 40, eps_r=True, mu_r=True)
