@@ -78,31 +78,29 @@ __device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *
     }
 }
 
-// Round two compute-type cells to the storage type (nearest even) and store them.
+// Buffer store of two field cells to a plane: raw buffer with the plane as its
+// range, so an offset at or beyond plane_bytes is dropped by the hardware range
+// check. Every lane issues the store every plane (lanes that must not write pass
+// kDrop), which keeps the number of memory operations after the prefetch loads
+// the same on every path; the wait for the prefetch then never covers stores.
+constexpr unsigned kDrop = 0x80000000u;
+constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
+
 template <typename S>
-__device__ __forceinline__ void stf(S *plane, unsigned boff, const typename V2<typename Store<S>::C>::type &x)
+__device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigned boff,
+                                         const typename V2<typename Store<S>::C>::type &x)
 {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, (int)plane_bytes, kRawBufferWord3);
     if constexpr (sizeof(S) == 2) {
         const S a = Store<S>::narrow(x[0]), b = Store<S>::narrow(x[1]);
         unsigned short ua, ub;
         __builtin_memcpy(&ua, &a, 2);
         __builtin_memcpy(&ub, &b, 2);
-        *(FDTD_GLOBAL unsigned *)(uni(plane) + boff) = (unsigned)ua | ((unsigned)ub << 16);
+        __builtin_amdgcn_raw_buffer_store_b32((unsigned)ua | ((unsigned)ub << 16), r, boff, 0, 0);
+    } else if constexpr (sizeof(S) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, boff, 0, 0);
     } else {
-        *(FDTD_GLOBAL typename V2<typename Store<S>::C>::type *)(uni(plane) + boff) = x;
-    }
-}
-
-template <typename S>
-__device__ __forceinline__ void stf1(S *plane, unsigned boff, typename Store<S>::C x)
-{
-    if constexpr (sizeof(S) == 2) {
-        const S a = Store<S>::narrow(x);
-        unsigned short ua;
-        __builtin_memcpy(&ua, &a, 2);
-        *(FDTD_GLOBAL unsigned short *)(uni(plane) + boff) = ua;
-    } else {
-        *(FDTD_GLOBAL S *)(uni(plane) + boff) = x;
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, boff, 0, 0);
     }
 }
 
@@ -177,7 +175,6 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     const int j = j0 - TS + row;
     const bool act = lane_ok && j >= 0 && j < ny && ib >= 0 && ib < nx;
     const bool own = main_wave && row >= TS && row < R - TS && act;
-    const bool full = ib + V <= nx;
     const unsigned offs = (unsigned)(ib + px * j) * (unsigned)sizeof(S);  // field byte offset in a plane
     const unsigned offc = (unsigned)(ib + px * j) * (unsigned)sizeof(T);  // coefficient byte offset
     const int lr = row + 1;     // LDS row
@@ -235,6 +232,10 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
         }
     }
     __syncthreads();  // LDS zeroing done
+    // vmcnt(0): the prologue loads land in registers the loop carries; without this wait the
+    // compiler's conservative merge at the loop head makes every plane wait for its own prefetch
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    const unsigned plane_bytes = (unsigned)(P * (long long)sizeof(S));
 
     for (int k = k0; k <= kend; ++k) {
         // ---------------- prefetch stage-1 inputs of plane k+1 ----------------
@@ -384,25 +385,20 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                         ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
                                             hxj[v]);
                 }
-                if (own && pp >= kb) {
-                    const long long pk = (long long)pp * P;
-                    if (full) {
-                        stf(dst.f[0] + pk, offs, ex);
-                        stf(dst.f[1] + pk, offs, ey);
-                        stf(dst.f[2] + pk, offs, ez);
-                        stf(dst.f[3] + pk, offs, hout[sp][0]);
-                        stf(dst.f[4] + pk, offs, hout[sp][1]);
-                        stf(dst.f[5] + pk, offs, hout[sp][2]);
-                    } else {
-                        // V = 2: only the first cell is in the domain
-                        stf1(dst.f[0] + pk, offs, ex[0]);
-                        stf1(dst.f[1] + pk, offs, ey[0]);
-                        stf1(dst.f[2] + pk, offs, ez[0]);
-                        stf1(dst.f[3] + pk, offs, hout[sp][0][0]);
-                        stf1(dst.f[4] + pk, offs, hout[sp][1][0]);
-                        stf1(dst.f[5] + pk, offs, hout[sp][2][0]);
-                    }
-                }
+            }
+            {
+                // unconditional stores (see st_plane); the cell at i = nx of a lane whose second
+                // cell leaves the domain carries its loaded, never-updated value (a wall or
+                // padding constant equal in both buffers), so storing both cells is exact
+                const bool wr = livep && own && pp >= kb;
+                const unsigned so = wr ? offs : kDrop;
+                const long long pk = (long long)(pp > 0 ? pp : 0) * P;
+                st_plane(dst.f[0] + pk, plane_bytes, so, ex);
+                st_plane(dst.f[1] + pk, plane_bytes, so, ey);
+                st_plane(dst.f[2] + pk, plane_bytes, so, ez);
+                st_plane(dst.f[3] + pk, plane_bytes, so, hout[sp][0]);
+                st_plane(dst.f[4] + pk, plane_bytes, so, hout[sp][1]);
+                st_plane(dst.f[5] + pk, plane_bytes, so, hout[sp][2]);
             }
             eout[sp][0] = ex;
             eout[sp][1] = ey;
