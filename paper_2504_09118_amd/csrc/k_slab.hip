@@ -97,6 +97,31 @@ __device__ __forceinline__ void st1(T *plane, unsigned boff, T x)
     *(FDTD_GLOBAL T *)(uni(plane) + boff) = x;
 }
 
+// Buffer store of a lane's V cells to a plane: raw buffer with the plane as its
+// range, so an offset at or beyond plane_bytes is dropped by the hardware range
+// check. Every lane issues the store every plane (lanes that must not write pass
+// kDrop), which keeps the number of memory operations after the prefetch loads
+// the same on every path; the wait for the prefetch then never covers stores.
+constexpr unsigned kDrop = 0x80000000u;
+constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
+
+template <typename T, int V>
+__device__ __forceinline__ void st_plane(T *plane, unsigned plane_bytes, unsigned boff,
+                                         const typename VecOf<T, V>::type &x)
+{
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, (int)plane_bytes, kRawBufferWord3);
+    constexpr int bytes = (int)sizeof(T) * V;
+    if constexpr (bytes == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, boff, 0, 0);
+    } else if constexpr (bytes == 8) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, boff, 0, 0);
+    } else {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, boff, 0, 0);
+    }
+}
+
 template <typename T, int V, int R, bool CE_ARR, bool CH_ARR>
 __global__ void __launch_bounds__(64 * R)
     k_slab(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles,
@@ -132,7 +157,6 @@ __global__ void __launch_bounds__(64 * R)
     const int ib = i0 + tx * V;
     const bool rowok = j >= 0 && j < ny;
     const bool act = rowok && ib < nx;            // lane has cells in the domain
-    const bool full = ib + V <= nx;               // all V cells in the domain
     const bool hrow = r < R - 1;                  // computes H (all but the E-provider row)
     const bool erow = r >= 1 && r < R - 1;        // owns its row: E update and stores
     // x-halo lanes: lane 0 rebuilds H at i0-1, lane 63 stages E at i0+TX
@@ -201,6 +225,11 @@ __global__ void __launch_bounds__(64 * R)
             xc = ld1(Ez + pk, xoff);
         }
     }
+
+    // vmcnt(0): the prologue loads land in registers the loop carries; without this wait the
+    // compiler's conservative merge at the loop head makes every plane wait for its own prefetch
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    const unsigned plane_bytes = (unsigned)(P * (long long)sizeof(T));
 
     for (int k = kstart; k < ke; ++k) {
         const bool own = k >= kb;
@@ -274,6 +303,8 @@ __global__ void __launch_bounds__(64 * R)
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int i = ib + v;
+                    if (i >= nx)
+                        continue;  // a cell past the domain keeps its loaded (constant) value
                     const T ez_ip = v + 1 < V ? el<T, V>(e2, v + 1) : ezr;
                     const T ey_ip = v + 1 < V ? el<T, V>(e1, v + 1) : eyr;
                     if (i >= 1)
@@ -285,19 +316,6 @@ __global__ void __launch_bounds__(64 * R)
                     if (k >= 1)
                         set_el<T, V>(hz, v, curl_update(el<T, V>(ho2, v), el<T, V>(ch2, v), el<T, V>(exj, v),
                                                         el<T, V>(e0, v), ey_ip, el<T, V>(e1, v)));
-                }
-                if (erow && own) {
-                    if (full) {
-                        st<T, V>(dst.f[3] + pk, off, hx);
-                        st<T, V>(dst.f[4] + pk, off, hy);
-                        st<T, V>(dst.f[5] + pk, off, hz);
-                    } else {
-                        for (int v = 0; v < V && ib + v < nx; ++v) {
-                            st1<T>(dst.f[3] + pk, off + v * (unsigned)sizeof(T), el<T, V>(hx, v));
-                            st1<T>(dst.f[4] + pk, off + v * (unsigned)sizeof(T), el<T, V>(hy, v));
-                            st1<T>(dst.f[5] + pk, off + v * (unsigned)sizeof(T), el<T, V>(hz, v));
-                        }
-                    }
                 }
             }
             *(vec *)&sH[0][r][HO + tx * V] = hx;
@@ -319,17 +337,27 @@ __global__ void __launch_bounds__(64 * R)
                 sH[0][r][HO - 1] = 0;
             }
         }
+        {
+            // unconditional stores (see st_plane): a cell at i >= nx carries its loaded,
+            // never-updated value (a wall or padding constant equal in both buffers)
+            const unsigned so = hrow && erow && act && own ? off : kDrop;
+            st_plane<T, V>(dst.f[3] + pk, plane_bytes, so, hx);
+            st_plane<T, V>(dst.f[4] + pk, plane_bytes, so, hy);
+            st_plane<T, V>(dst.f[5] + pk, plane_bytes, so, hz);
+        }
         __syncthreads();
         // ---------------- E^{n+1} at plane k ----------------
+        vec ex = e0, ey = e1, ez = e2;
         if (erow && act && own) {
             const vec hzj = *(const vec *)&sH[2][r - 1][HO + tx * V];  // Hz(i, j-1)
             const vec hxj = *(const vec *)&sH[0][r - 1][HO + tx * V];  // Hx(i, j-1)
             const T hzl = sH[2][r][HO + tx * V - 1];                   // Hz(ib-1, j)
             const T hyl = sH[1][r][HO + tx * V - 1];                   // Hy(ib-1, j)
-            vec ex = e0, ey = e1, ez = e2;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const int i = ib + v;
+                if (i >= nx)
+                    continue;
                 const T hz_im = v > 0 ? el<T, V>(hz, v - 1) : hzl;
                 const T hy_im = v > 0 ? el<T, V>(hy, v - 1) : hyl;
                 if (j >= 1 && k >= 1)
@@ -342,17 +370,12 @@ __global__ void __launch_bounds__(64 * R)
                     set_el<T, V>(ez, v, curl_update(el<T, V>(e2, v), el<T, V>(ce2, v), el<T, V>(hy, v), hy_im,
                                                     el<T, V>(hx, v), el<T, V>(hxj, v)));
             }
-            if (full) {
-                st<T, V>(dst.f[0] + pk, off, ex);
-                st<T, V>(dst.f[1] + pk, off, ey);
-                st<T, V>(dst.f[2] + pk, off, ez);
-            } else {
-                for (int v = 0; v < V && ib + v < nx; ++v) {
-                    st1<T>(dst.f[0] + pk, off + v * (unsigned)sizeof(T), el<T, V>(ex, v));
-                    st1<T>(dst.f[1] + pk, off + v * (unsigned)sizeof(T), el<T, V>(ey, v));
-                    st1<T>(dst.f[2] + pk, off + v * (unsigned)sizeof(T), el<T, V>(ez, v));
-                }
-            }
+        }
+        {
+            const unsigned so = erow && act && own ? off : kDrop;
+            st_plane<T, V>(dst.f[0] + pk, plane_bytes, so, ex);
+            st_plane<T, V>(dst.f[1] + pk, plane_bytes, so, ey);
+            st_plane<T, V>(dst.f[2] + pk, plane_bytes, so, ez);
         }
         // ---------------- rotate the pipeline ----------------
         hpx = hx;
