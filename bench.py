@@ -27,7 +27,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-STORAGE_LABEL = {"f32": "FP32", "f16": "FP16", "bf16": "BF16"}
+STORAGE_LABEL = {"f32": "FP32", "f16": "FP16", "bf16": "BF16", "f16c": "FP16+int8 residual",
+                 "bf16c": "BF16+int8 residual"}
+FIELD_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "f16c": 3, "bf16c": 3}
 
 
 def algorithmic_bytes_per_cell_step(kernel: str, ce_arrays: bool, ch_arrays: bool, field_bytes: int = 4,
@@ -77,7 +79,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=512, help="cells per axis")
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--tb-steps", type=int, default=0)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f16c", "bf16c"],
                     help="device field storage (16-bit fields compute in FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=60)
@@ -151,7 +153,7 @@ def main() -> int:
     launches = sweeps * launches_per_sweep
     avg_launch_s = secs / launches
     b_sweep = algorithmic_bytes_per_cell_step(kernel, q["ce_array"], q["ch_array"],
-                                              field_bytes=2 if args.storage in ("f16", "bf16") else 4)
+                                              field_bytes=FIELD_BYTES[args.storage])
     bytes_per_launch = b_sweep * cells / launches_per_sweep
     achieved = bytes_per_launch * launches / secs / 1e9
     traffic, traffic_src = (None, None)

@@ -65,8 +65,21 @@ typedef enum {
  * or FDTD_BF16 (bfloat16); such fields are widened to FP32 on load, a sweep
  * computes in FP32 (coefficients stay FP32) and rounds to nearest even once
  * when it stores, i.e. once per sweep of tb_steps steps.
+ * Compensated storage (FDTD_F16C, FDTD_BF16C) keeps, next to each 16-bit value
+ * hi, the rounding residual of the FP32 value x it stands for: q = rint((x -
+ * hi) / s) in [-127, 127] as an int8, s = ulp(hi) / 256 (a power of two from
+ * hi's exponent). The value is hi + q s, exact in FP32 and within ulp(hi)/512
+ * of x: 3 bytes per value, about 2^-20 (FP16) or 2^-17 (BF16) relative per
+ * store instead of 2^-11 or 2^-8. Built for the temporal kernel.
  */
-typedef enum { FDTD_F64 = 0, FDTD_F32 = 1, FDTD_F16 = 2, FDTD_BF16 = 3 } fdtd_dtype;
+typedef enum {
+    FDTD_F64 = 0,
+    FDTD_F32 = 1,
+    FDTD_F16 = 2,
+    FDTD_BF16 = 3,
+    FDTD_F16C = 4,  /* compensated FP16: see below */
+    FDTD_BF16C = 5  /* compensated BF16 */
+} fdtd_dtype;
 
 /* Field indices in the six-pointer arrays. */
 enum { FDTD_EX = 0, FDTD_EY, FDTD_EZ, FDTD_HX, FDTD_HY, FDTD_HZ };
@@ -95,8 +108,8 @@ typedef struct {
 } fdtd_coef;
 
 typedef struct {
-    int storage;        /* fdtd_dtype of device fields: FDTD_F32 (default), FDTD_F64, FDTD_F16, FDTD_BF16
-                           (16-bit storage runs the temporal kernel only) */
+    int storage;        /* fdtd_dtype of device fields: FDTD_F32 (default), FDTD_F64, FDTD_F16, FDTD_BF16,
+                           FDTD_F16C, FDTD_BF16C (16-bit based storage runs the temporal kernel only) */
     int kernel;         /* fdtd_kernel, default FDTD_KERNEL_AUTO */
     int tb_steps;       /* steps per sweep for FDTD_KERNEL_TEMPORAL (0: library default) */
     int device;         /* HIP device ordinal, default 0 */

@@ -35,7 +35,7 @@ std::string &g_last_error_ref()
 }  // namespace
 
 namespace fdtd {
-Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool aux)
+Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool aux, bool comp)
 {
     auto up = [](size_t v, size_t a) { return (v + a - 1) / a * a; };
     Plan p{};
@@ -50,7 +50,8 @@ Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool 
     g.box = (long long)up((size_t)g.plane * g.pz + 2 * kGuardElems, 64);
     p.fesz = (size_t)fesz;
     p.cesz = fesz == 8 ? 8 : 4;  // 16-bit fields keep FP32 coefficients
-    p.fbox_bytes = up((size_t)g.box * p.fesz, 256);
+    p.fbox_bytes = up((size_t)g.box * p.fesz, 256) + (comp ? up((size_t)g.box, 256) : 0);
+    g.lo_off = comp ? (long long)up((size_t)g.box * p.fesz, 256) + kGuardElems - (long long)kGuardElems * fesz : 0;
     p.cbox_bytes = up((size_t)g.box * p.cesz, 256);
     size_t off = 0;
     for (int b = 0; b < 2; ++b)
@@ -128,9 +129,12 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 using fdtd::Plan;
 
+bool is_comp(int storage) { return storage == FDTD_F16C || storage == FDTD_BF16C; }
+
 Plan make_plan(int nx, int ny, int nz, int storage, bool ce_arr, bool ch_arr)
 {
-    return fdtd::make_plan(nx, ny, nz, storage == FDTD_F64 ? 8 : storage == FDTD_F32 ? 4 : 2, ce_arr, ch_arr, true);
+    return fdtd::make_plan(nx, ny, nz, storage == FDTD_F64 ? 8 : storage == FDTD_F32 ? 4 : 2, ce_arr, ch_arr, true,
+                           is_comp(storage));
 }
 
 }  // namespace
@@ -194,11 +198,17 @@ auto by_storage(int storage, Fn &&fn)
     case FDTD_F64: return fn(double{});
     case FDTD_F16: return fn(fdtd::f16{});
     case FDTD_BF16: return fn(fdtd::bf16{});
+    case FDTD_F16C: return fn(fdtd::f16c{});
+    case FDTD_BF16C: return fn(fdtd::bf16c{});
     default: return fn(float{});
     }
 }
 
-bool is16(int storage) { return storage == FDTD_F16 || storage == FDTD_BF16; }
+// 16-bit based storage (plain or compensated): built for the temporal kernel only
+bool is16(int storage)
+{
+    return storage == FDTD_F16 || storage == FDTD_BF16 || storage == FDTD_F16C || storage == FDTD_BF16C;
+}
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
@@ -424,7 +434,7 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
     fdtd_opts d;
     fdtd_opts_default(&d);
     const fdtd_opts *o = opts ? opts : &d;
-    if (o->storage < FDTD_F64 || o->storage > FDTD_BF16)
+    if (o->storage < FDTD_F64 || o->storage > FDTD_BF16C)
         return fail(FDTD_E_UNSUPPORTED, "storage dtype %d not built", o->storage);
     const bool rect = (o->dy > 0.0 || o->dz > 0.0);  // rectangular cells keep per-node coefficient arrays
     Plan p = make_plan(nx, ny, nz, o->storage, (coef && coef->eps_r) || rect, (coef && coef->mu_r) || rect);
@@ -446,7 +456,7 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     fdtd_opts d;
     fdtd_opts_default(&d);
     const fdtd_opts *o = opts ? opts : &d;
-    if (o->storage < FDTD_F64 || o->storage > FDTD_BF16)
+    if (o->storage < FDTD_F64 || o->storage > FDTD_BF16C)
         return fail(FDTD_E_UNSUPPORTED, "storage dtype %d not built", o->storage);
     if (o->kernel < FDTD_KERNEL_AUTO || o->kernel > FDTD_KERNEL_TEMPORAL)
         return fail(FDTD_E_ARG, "unknown kernel %d", o->kernel);

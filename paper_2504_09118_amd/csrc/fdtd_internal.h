@@ -31,6 +31,8 @@ struct Geom {
     int px, py, pz;
     long long plane;  // px * py
     long long box;    // elements reserved per component box (incl. guards, 64-aligned)
+    long long lo_off; // compensated 16-bit storage: byte offset from a box's element 0 to
+                      // its residual box's element 0 (0 otherwise)
     __host__ __device__ long long at(int i, int j, int k) const
     {
         return (long long)i + (long long)px * ((long long)j + (long long)py * k);
@@ -114,8 +116,9 @@ struct Plan {
     size_t total;
 };
 
-// fesz: 8, 4 or 2 bytes; coefficients are FP64 for FP64 fields, else FP32.
-Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool aux);
+// fesz: 8, 4 or 2 bytes; coefficients are FP64 for FP64 fields, else FP32. comp: each
+// field box also carries an int8 residual box (compensated 16-bit storage).
+Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool aux, bool comp = false);
 
 // Seeded random state (E ~ U[-1,1] from a counter-based SplitMix64, PEC walls,
 // H = 0) written into both state buffers a and b (b may hold nullptrs).

@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(kBlock) k_init_random(Geom g, int field, int X
     const long long r = l / X;
     const int j = (int)(r % Y);
     const int k = (int)(r / Y);
-    T v = Store<T>::narrow(0);
+    typename Store<T>::C v = 0;
     if (field < 3) {
         bool wall;
         if (field == 0)
@@ -48,13 +48,13 @@ __global__ void __launch_bounds__(kBlock) k_init_random(Geom g, int field, int X
             const unsigned long long c = ((unsigned long long)field << 40) + (unsigned long long)l;
             const unsigned long long z = mix64(seed + (c + 1ull) * 0x9E3779B97F4A7C15ull);
             const double u = (double)(z >> 11) * 0x1.0p-53;
-            v = Store<T>::narrow(to_compute<T>((2.0 * u - 1.0) * scale));  // exact for scale 1
+            v = to_compute<T>((2.0 * u - 1.0) * scale);  // exact for scale 1
         }
     }
     const long long o = g.at(i, j, k);
-    dst[o] = v;
+    put_elem(dst, g.lo_off, o, v);
     if (dst2)
-        dst2[o] = v;
+        put_elem(dst2, g.lo_off, o, v);
 }
 
 }  // namespace
@@ -82,6 +82,10 @@ template hipError_t launch_init_random<double>(const Geom &, unsigned long long,
                                                double *const[6], hipStream_t, const double *);
 template hipError_t launch_init_random<f16>(const Geom &, unsigned long long, f16 *const[6], f16 *const[6],
                                             hipStream_t, const double *);
+template hipError_t launch_init_random<f16c>(const Geom &, unsigned long long, f16c *const[6], f16c *const[6],
+                                             hipStream_t, const double *);
+template hipError_t launch_init_random<bf16c>(const Geom &, unsigned long long, bf16c *const[6], bf16c *const[6],
+                                              hipStream_t, const double *);
 template hipError_t launch_init_random<bf16>(const Geom &, unsigned long long, bf16 *const[6], bf16 *const[6],
                                              hipStream_t, const double *);
 

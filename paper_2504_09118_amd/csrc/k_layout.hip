@@ -42,13 +42,13 @@ __global__ void __launch_bounds__(kBlock) k_pack(Geom g, int field, int X, int Y
     int i, j, k;
     unflatten(l, X, Y, i, j, k);
     // scaled in FP64 (exact for scale 1); 16-bit storage: rounded to FP32, then to the 16-bit type
-    T v = Store<T>::narrow(to_compute<T>((double)src[l] * scale));
+    typename Store<T>::C v = to_compute<T>((double)src[l] * scale);
     if (e_wall(field, i, j, k, g.nx, g.ny, g.nz))
-        v = Store<T>::narrow(0);
+        v = 0;
     long long o = g.at(i, j, k);
-    dst[o] = v;
+    put_elem(dst, g.lo_off, o, v);
     if (dst2)
-        dst2[o] = v;
+        put_elem(dst2, g.lo_off, o, v);
 }
 
 template <typename T, typename S>
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(kBlock) k_unpack(Geom g, int X, int Y, long lo
         return;
     int i, j, k;
     unflatten(l, X, Y, i, j, k);
-    dst[l] = (S)((double)Store<T>::widen(src[g.at(i, j, k)]) / scale);
+    dst[l] = (S)((double)get_elem(src, g.lo_off, g.at(i, j, k)) / scale);
 }
 
 __device__ __forceinline__ double mat(const double *m, int nx, int ny, int i, int j, int k)
@@ -172,6 +172,16 @@ template hipError_t launch_pack<float, f16>(const Geom &, int, const float *, f1
 template hipError_t launch_pack<double, f16>(const Geom &, int, const double *, f16 *, f16 *, hipStream_t, double);
 template hipError_t launch_pack<float, bf16>(const Geom &, int, const float *, bf16 *, bf16 *, hipStream_t, double);
 template hipError_t launch_pack<double, bf16>(const Geom &, int, const double *, bf16 *, bf16 *, hipStream_t, double);
+template hipError_t launch_pack<float, f16c>(const Geom &, int, const float *, f16c *, f16c *, hipStream_t, double);
+template hipError_t launch_pack<double, f16c>(const Geom &, int, const double *, f16c *, f16c *, hipStream_t, double);
+template hipError_t launch_pack<float, bf16c>(const Geom &, int, const float *, bf16c *, bf16c *, hipStream_t,
+                                              double);
+template hipError_t launch_pack<double, bf16c>(const Geom &, int, const double *, bf16c *, bf16c *, hipStream_t,
+                                               double);
+template hipError_t launch_unpack<f16c, float>(const Geom &, int, const f16c *, float *, hipStream_t, double);
+template hipError_t launch_unpack<f16c, double>(const Geom &, int, const f16c *, double *, hipStream_t, double);
+template hipError_t launch_unpack<bf16c, float>(const Geom &, int, const bf16c *, float *, hipStream_t, double);
+template hipError_t launch_unpack<bf16c, double>(const Geom &, int, const bf16c *, double *, hipStream_t, double);
 template hipError_t launch_unpack<f16, float>(const Geom &, int, const f16 *, float *, hipStream_t, double);
 template hipError_t launch_unpack<f16, double>(const Geom &, int, const f16 *, double *, hipStream_t, double);
 template hipError_t launch_unpack<bf16, float>(const Geom &, int, const bf16 *, float *, hipStream_t, double);

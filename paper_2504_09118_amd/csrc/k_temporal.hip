@@ -59,8 +59,11 @@ __device__ __forceinline__ typename V2<T>::type ld2(const T *plane, unsigned bof
 }
 
 // Two consecutive field cells of storage type S, widened to the compute type.
+// Compensated storage also reads the two residuals from lo_plane, the same
+// plane of the residual box (one byte per cell).
 template <typename S>
-__device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *plane, unsigned boff)
+__device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *plane, unsigned boff,
+                                                                       const char *lo_plane)
 {
     using C = typename Store<S>::C;
     if constexpr (sizeof(S) == 2) {
@@ -70,10 +73,17 @@ __device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *
         __builtin_memcpy(&a, &ua, 2);
         __builtin_memcpy(&b, &ub, 2);
         typename V2<C>::type r;
-        r[0] = Store<S>::widen(a);
-        r[1] = Store<S>::widen(b);
+        if constexpr (Store<S>::comp) {
+            const unsigned short q = *(FDTD_GLOBAL const unsigned short *)(uni(lo_plane) + boff / 2);
+            r[0] = Store<S>::dec(a, (signed char)(q & 0xff));
+            r[1] = Store<S>::dec(b, (signed char)(q >> 8));
+        } else {
+            r[0] = Store<S>::widen(a);
+            r[1] = Store<S>::widen(b);
+        }
         return r;
     } else {
+        (void)lo_plane;
         return *(FDTD_GLOBAL const typename V2<C>::type *)(uni(plane) + boff);
     }
 }
@@ -87,19 +97,36 @@ constexpr unsigned kDrop = 0x80000000u;
 constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
 
 template <typename S>
-__device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigned boff,
+__device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigned boff, char *lo_plane,
                                          const typename V2<typename Store<S>::C>::type &x)
 {
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, (int)plane_bytes, kRawBufferWord3);
     if constexpr (sizeof(S) == 2) {
-        const S a = Store<S>::narrow(x[0]), b = Store<S>::narrow(x[1]);
+        S a, b;
+        signed char qa = 0, qb = 0;
+        if constexpr (Store<S>::comp) {
+            Store<S>::enc(x[0], a, qa);
+            Store<S>::enc(x[1], b, qb);
+        } else {
+            a = Store<S>::narrow(x[0]);
+            b = Store<S>::narrow(x[1]);
+        }
         unsigned short ua, ub;
         __builtin_memcpy(&ua, &a, 2);
         __builtin_memcpy(&ub, &b, 2);
         __builtin_amdgcn_raw_buffer_store_b32((unsigned)ua | ((unsigned)ub << 16), r, boff, 0, 0);
+        if constexpr (Store<S>::comp) {
+            // residual box: one byte per cell, the same plane layout (a dropped offset stays dropped)
+            const __amdgpu_buffer_rsrc_t rq =
+                __builtin_amdgcn_make_buffer_rsrc(lo_plane, 0, (int)(plane_bytes / 2), kRawBufferWord3);
+            const unsigned short q = (unsigned short)((unsigned char)qa | ((unsigned)(unsigned char)qb << 8));
+            __builtin_amdgcn_raw_buffer_store_b16(q, rq, boff / 2, 0, 0);
+        }
     } else if constexpr (sizeof(S) == 4) {
+        (void)lo_plane;
         __builtin_amdgcn_raw_buffer_store_b64(x, r, boff, 0, 0);
     } else {
+        (void)lo_plane;
         __builtin_amdgcn_raw_buffer_store_b128(x, r, boff, 0, 0);
     }
 }
@@ -180,6 +207,10 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     const int lr = row + 1;     // LDS row
     const int lc = HX + c0;     // LDS column of the first cell
 
+    // residual plane of a compensated box (a field pointer points at element 0; the residual
+    // box holds one byte per element, lo_off bytes past it)
+    auto lp = [&](const S *base, long long pk) { return (const char *)base + g.lo_off + pk; };
+    auto lq = [&](S *base, long long pk) { return (char *)base + g.lo_off + pk; };
     const S *Ex = src.f[0], *Ey = src.f[1], *Ez = src.f[2];
     const S *Hx = src.f[3], *Hy = src.f[4], *Hz = src.f[5];
     const vec zero = (vec)(T)0;
@@ -209,17 +240,17 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     // first planes of stage 1
     if (act) {
         const long long pk = (long long)k0 * P;
-        Ecur[0][0] = ldf(Ex + pk, offs);
-        Ecur[0][1] = ldf(Ey + pk, offs);
-        Ecur[0][2] = ldf(Ez + pk, offs);
+        Ecur[0][0] = ldf(Ex + pk, offs, lp(Ex, pk));
+        Ecur[0][1] = ldf(Ey + pk, offs, lp(Ey, pk));
+        Ecur[0][2] = ldf(Ez + pk, offs, lp(Ez, pk));
         if (k0 + 1 < nz) {
-            En1[0] = ldf(Ex + pk + P, offs);
-            En1[1] = ldf(Ey + pk + P, offs);
-            En1[2] = ldf(Ez + pk + P, offs);
+            En1[0] = ldf(Ex + pk + P, offs, lp(Ex, pk + P));
+            En1[1] = ldf(Ey + pk + P, offs, lp(Ey, pk + P));
+            En1[2] = ldf(Ez + pk + P, offs, lp(Ez, pk + P));
         }
-        Hold[0][0] = ldf(Hx + pk, offs);
-        Hold[0][1] = ldf(Hy + pk, offs);
-        Hold[0][2] = ldf(Hz + pk, offs);
+        Hold[0][0] = ldf(Hx + pk, offs, lp(Hx, pk));
+        Hold[0][1] = ldf(Hy + pk, offs, lp(Hy, pk));
+        Hold[0][2] = ldf(Hz + pk, offs, lp(Hz, pk));
         if (CE_ARR) {
             Ce[0][0] = ld2(c.ce[0] + pk, offc);
             Ce[0][1] = ld2(c.ce[1] + pk, offc);
@@ -244,13 +275,13 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
         if (act && k + 1 <= kend && k + 1 < nz) {
             const long long pk1 = (long long)(k + 1) * P;
             if (k + 2 < nz) {
-                pE[0] = ldf(Ex + pk1 + P, offs);
-                pE[1] = ldf(Ey + pk1 + P, offs);
-                pE[2] = ldf(Ez + pk1 + P, offs);
+                pE[0] = ldf(Ex + pk1 + P, offs, lp(Ex, pk1 + P));
+                pE[1] = ldf(Ey + pk1 + P, offs, lp(Ey, pk1 + P));
+                pE[2] = ldf(Ez + pk1 + P, offs, lp(Ez, pk1 + P));
             }
-            pH[0] = ldf(Hx + pk1, offs);
-            pH[1] = ldf(Hy + pk1, offs);
-            pH[2] = ldf(Hz + pk1, offs);
+            pH[0] = ldf(Hx + pk1, offs, lp(Hx, pk1));
+            pH[1] = ldf(Hy + pk1, offs, lp(Hy, pk1));
+            pH[2] = ldf(Hz + pk1, offs, lp(Hz, pk1));
             if (CE_ARR) {
                 pCe[0] = ld2(c.ce[0] + pk1, offc);
                 pCe[1] = ld2(c.ce[1] + pk1, offc);
@@ -393,12 +424,12 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                 const bool wr = livep && own && pp >= kb;
                 const unsigned so = wr ? offs : kDrop;
                 const long long pk = (long long)(pp > 0 ? pp : 0) * P;
-                st_plane(dst.f[0] + pk, plane_bytes, so, ex);
-                st_plane(dst.f[1] + pk, plane_bytes, so, ey);
-                st_plane(dst.f[2] + pk, plane_bytes, so, ez);
-                st_plane(dst.f[3] + pk, plane_bytes, so, hout[sp][0]);
-                st_plane(dst.f[4] + pk, plane_bytes, so, hout[sp][1]);
-                st_plane(dst.f[5] + pk, plane_bytes, so, hout[sp][2]);
+                st_plane(dst.f[0] + pk, plane_bytes, so, lq(dst.f[0], pk), ex);
+                st_plane(dst.f[1] + pk, plane_bytes, so, lq(dst.f[1], pk), ey);
+                st_plane(dst.f[2] + pk, plane_bytes, so, lq(dst.f[2], pk), ez);
+                st_plane(dst.f[3] + pk, plane_bytes, so, lq(dst.f[3], pk), hout[sp][0]);
+                st_plane(dst.f[4] + pk, plane_bytes, so, lq(dst.f[4], pk), hout[sp][1]);
+                st_plane(dst.f[5] + pk, plane_bytes, so, lq(dst.f[5], pk), hout[sp][2]);
             }
             eout[sp][0] = ex;
             eout[sp][1] = ey;
@@ -583,6 +614,10 @@ template hipError_t launch_temporal_step<f16>(const Geom &, const Fields<f16> &,
                                               const Coefs<float> &, int, int, int, hipStream_t);
 template hipError_t launch_temporal_step<bf16>(const Geom &, const Fields<bf16> &, const Fields<bf16> &,
                                                const Coefs<float> &, int, int, int, hipStream_t);
+template hipError_t launch_temporal_step<f16c>(const Geom &, const Fields<f16c> &, const Fields<f16c> &,
+                                               const Coefs<float> &, int, int, int, hipStream_t);
+template hipError_t launch_temporal_step<bf16c>(const Geom &, const Fields<bf16c> &, const Fields<bf16c> &,
+                                                const Coefs<float> &, int, int, int, hipStream_t);
 
 }  // namespace fdtd
 

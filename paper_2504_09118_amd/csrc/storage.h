@@ -46,12 +46,23 @@ __host__ __device__ inline bf16 float_to_bf16(float f)
     return r;
 }
 
+// Compensated 16-bit storage: the 16-bit value (array of these) plus, in a
+// parallel int8 box, its rounding residual in units of 1/256 of the 16-bit
+// ulp. Three bytes per value; decoding is exact in FP32.
+struct f16c {
+    _Float16 h;
+};
+struct bf16c {
+    unsigned short u;
+};
+
 template <typename S>
 struct Store;
 
 template <>
 struct Store<float> {
     using C = float;
+    static constexpr bool comp = false;
     __host__ __device__ static C widen(float v) { return v; }
     __host__ __device__ static float narrow(C v) { return v; }
 };
@@ -59,6 +70,7 @@ struct Store<float> {
 template <>
 struct Store<double> {
     using C = double;
+    static constexpr bool comp = false;
     __host__ __device__ static C widen(double v) { return v; }
     __host__ __device__ static double narrow(C v) { return v; }
 };
@@ -66,6 +78,7 @@ struct Store<double> {
 template <>
 struct Store<f16> {
     using C = float;
+    static constexpr bool comp = false;
     __host__ __device__ static C widen(f16 v) { return (float)v; }
     __host__ __device__ static f16 narrow(C v) { return (f16)v; }
 };
@@ -73,9 +86,119 @@ struct Store<f16> {
 template <>
 struct Store<bf16> {
     using C = float;
+    static constexpr bool comp = false;
     __host__ __device__ static C widen(bf16 v) { return bf16_to_float(v); }
     __host__ __device__ static bf16 narrow(C v) { return float_to_bf16(v); }
 };
+
+__host__ __device__ inline unsigned f32_bits(float f)
+{
+    union {
+        unsigned u;
+        float f;
+    } x;
+    x.f = f;
+    return x.u;
+}
+
+__host__ __device__ inline float bits_f32(unsigned u)
+{
+    union {
+        unsigned u;
+        float f;
+    } x;
+    x.u = u;
+    return x.f;
+}
+
+// Compensated encoding of an FP32 value x: hi = x rounded to the 16-bit type
+// (nearest even), r = x - hi (exact), residual q = rint(r / s) clamped to
+// [-127, 127] with s = ulp(hi) / 256, a power of two taken from hi's exponent
+// field e as 2^(max(e, e_min) - bias - mantissa_bits - 8). Decoding hi + q s is
+// exact in FP32; the stored value is within s / 2 of x (ulp/512, 2^-20
+// relative for FP16, 2^-17 for BF16).
+__host__ __device__ inline float comp_scale_f16(unsigned short hbits)
+{
+    int e = (hbits >> 10) & 0x1f;
+    e = e < 1 ? 1 : e;
+    return bits_f32((unsigned)(e - 15 - 10 - 8 + 127) << 23);
+}
+
+__host__ __device__ inline float comp_scale_bf16(unsigned short hbits)
+{
+    int e = (hbits >> 7) & 0xff;
+    e = e < 16 ? 16 : e;  // keeps the scale a normal FP32 number
+    return bits_f32((unsigned)(e - 127 - 7 - 8 + 127) << 23);
+}
+
+__host__ __device__ inline signed char comp_residual(float x, float hi, float scale)
+{
+    float q = __builtin_rintf((x - hi) / scale);  // the division is exact: scale is a power of two
+    q = q > 127.0f ? 127.0f : (q < -127.0f ? -127.0f : q);
+    return (signed char)(int)q;
+}
+
+template <>
+struct Store<f16c> {
+    using C = float;
+    static constexpr bool comp = true;
+    __host__ __device__ static unsigned short bits(f16c v)
+    {
+        unsigned short u;
+        __builtin_memcpy(&u, &v, 2);
+        return u;
+    }
+    __host__ __device__ static C dec(f16c hi, signed char q)
+    {
+        return (float)hi.h + (float)q * comp_scale_f16(bits(hi));
+    }
+    __host__ __device__ static void enc(C x, f16c &hi, signed char &q)
+    {
+        hi.h = (_Float16)x;
+        q = comp_residual(x, (float)hi.h, comp_scale_f16(bits(hi)));
+    }
+};
+
+template <>
+struct Store<bf16c> {
+    using C = float;
+    static constexpr bool comp = true;
+    __host__ __device__ static C dec(bf16c hi, signed char q)
+    {
+        return bf16_to_float(bf16{hi.u}) + (float)q * comp_scale_bf16(hi.u);
+    }
+    __host__ __device__ static void enc(C x, bf16c &hi, signed char &q)
+    {
+        hi.u = float_to_bf16(x).u;
+        q = comp_residual(x, bf16_to_float(bf16{hi.u}), comp_scale_bf16(hi.u));
+    }
+};
+
+// Element access through the storage rules. lo_off: byte distance from a
+// compensated box's element 0 to its residual box's element 0 (unused for
+// the plain types).
+template <typename T>
+__host__ __device__ inline typename Store<T>::C get_elem(const T *a, long long lo_off, long long o)
+{
+    if constexpr (Store<T>::comp)
+        return Store<T>::dec(a[o], ((const signed char *)a + lo_off)[o]);
+    else
+        return Store<T>::widen(a[o]);
+}
+
+template <typename T>
+__host__ __device__ inline void put_elem(T *a, long long lo_off, long long o, typename Store<T>::C v)
+{
+    if constexpr (Store<T>::comp) {
+        T h;
+        signed char q;
+        Store<T>::enc(v, h, q);
+        a[o] = h;
+        ((signed char *)a + lo_off)[o] = q;
+    } else {
+        a[o] = Store<T>::narrow(v);
+    }
+}
 
 // Source value -> compute type of storage T, rounded once to nearest even.
 // For 16-bit T and an FP64 source the FP32 value is pinned in a register

@@ -16,8 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
 OK, E_ARG, E_CFL, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
-F64, F32, F16, BF16 = 0, 1, 2, 3
-STORAGE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+F64, F32, F16, BF16, F16C, BF16C = 0, 1, 2, 3, 4, 5
+STORAGE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f16c": F16C, "bf16c": BF16C}
 STORAGE_NAMES = {v: k for k, v in STORAGE.items()}
 KERNELS = {"auto": 0, "plain": 1, "fused": 2, "slab": 3, "temporal": 4}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
@@ -240,8 +240,9 @@ def required_bytes(nx, ny, nz, eps_r=None, mu_r=None, storage="f32", kernel="aut
 class Solver:
     """One PEC-cavity Yee solver living on one GPU.
 
-    storage: "f32" (default), "f64" (test-only double-precision fields), or
-    "f16" / "bf16" (16-bit fields computed in FP32, rounded once per sweep).
+    storage: "f32" (default), "f64" (test-only double-precision fields),
+    "f16" / "bf16" (16-bit fields computed in FP32, rounded once per sweep), or
+    "f16c" / "bf16c" (16-bit value plus an int8 residual: compensated, 3 bytes).
     kernel: "auto", "plain", "fused", "slab" or "temporal"; tb_steps: steps
     per sweep for "temporal".
     stream: a hipStream_t handle (int), a torch.cuda.Stream, or "torch" for

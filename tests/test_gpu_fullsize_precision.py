@@ -23,7 +23,7 @@ S = 0.5 / math.sqrt(3.0)
 STEPS = 500
 # stated bounds (rel-L2 vs the FP64 oracle after 500 steps at 512^3, tb = 3; measured
 # 5.6e-6, 2.83e-3, 2.27e-2)
-BOUND = {"f32": 1e-5, "f16": 5e-3, "bf16": 4e-2}
+BOUND = {"f32": 1e-5, "f16": 5e-3, "bf16": 4e-2, "f16c": 1e-4, "bf16c": 1e-3}
 
 
 def _P():
@@ -54,7 +54,7 @@ def test_512_precision_vs_oracle():
     oracle.run(ref, ce, ch, STEPS)
     del ce, ch
     den = math.sqrt(sum(float(np.dot(r.ravel(), r.ravel())) for r in ref))
-    for storage in ("f32", "f16", "bf16"):
+    for storage in ("f32", "f16", "bf16", "f16c", "bf16c"):
         got = gpu_fields(n, eps, e32, storage, stream)
         num = 0.0
         for g, r in zip(got, ref):
@@ -81,7 +81,7 @@ def test_1024_16bit_vs_fp32():
         s.get_fields_device(ref)
         s.sync()
     den = math.sqrt(sum(float(torch.sum(r.double() ** 2)) for r in ref))
-    for storage in ("f16", "bf16"):
+    for storage in ("f16", "bf16", "f16c", "bf16c"):
         got = [torch.empty(sh, dtype=torch.float32, device="cuda") for sh in shapes]
         with P.Solver(n, n, n, 1.0, S, eps_r=eps, storage=storage, stream=stream) as s:
             s.init_random(3)

@@ -37,11 +37,30 @@ def round_bf16(a):
     return out
 
 
+def comp_store(a, storage):
+    """Compensated storage of FP32 values: 16-bit hi plus rint((x - hi)/s) in [-127, 127],
+    s = ulp(hi)/256 from hi's exponent field; returns hi + q s (exact in FP32) as FP64."""
+    x = np.asarray(a, dtype=np.float32)
+    if storage == "f16c":
+        hi = x.astype(np.float16)
+        e = np.maximum((hi.view(np.uint16).astype(np.int64) >> 10) & 0x1F, 1)
+        scale = np.ldexp(np.float32(1.0), e - 15 - 10 - 8).astype(np.float32)
+        hif = hi.astype(np.float32)
+    else:
+        hif = round_bf16(x).astype(np.float32)
+        e = np.maximum((hif.view(np.uint32).astype(np.int64) >> 23) & 0xFF, 16)
+        scale = np.ldexp(np.float32(1.0), e - 127 - 7 - 8).astype(np.float32)
+    q = np.clip(np.rint((x - hif) / scale), -127, 127).astype(np.float32)
+    return (hif + q * scale).astype(np.float64)
+
+
 def round_store(a, storage):
     if storage == "f16":
         return np.asarray(a, dtype=np.float32).astype(np.float16).astype(np.float64)
     if storage == "bf16":
         return round_bf16(a)
+    if storage in ("f16c", "bf16c"):
+        return comp_store(a, storage)
     raise ValueError(storage)
 
 
@@ -73,6 +92,10 @@ CASES = [
     ((32, 32, 32), 1000, 3, "f16", 6e-3),
     ((32, 32, 32), 1000, 3, "bf16", 5e-2),
     ((40, 36, 44), 300, 2, "f16", 4e-3),
+    ((32, 32, 32), 100, 3, "f16c", 1e-5),
+    ((32, 32, 32), 100, 3, "bf16c", 1e-4),
+    ((32, 32, 32), 1000, 3, "f16c", 3e-5),
+    ((32, 32, 32), 1000, 3, "bf16c", 3e-4),
 ]
 
 
@@ -94,7 +117,10 @@ def test_16bit_storage_error(dims, steps, tb, storage, bound):
     print(f"\n{storage} {dims} {steps} steps tb={tb}: rel-L2 vs FP64 oracle {err_exact:.3e} "
           f"(FP32 emulation of the {storage} storage rule: {err_emu:.3e})")
     assert err_exact < bound
-    assert abs(err_exact - err_emu) < 0.15 * err_emu
+    # compensated storage: the storage error is only ~16x the FP32 rounding, so the FMA
+    # (GPU) vs separate-rounding (emulation) difference shows; 30 % instead of 15 %
+    tol = 0.3 if storage.endswith("c") else 0.15
+    assert abs(err_exact - err_emu) < tol * err_emu
     assert oracle.tangential_max(got) == 0.0
     assert d["nonfinite"] == 0
 
@@ -112,6 +138,24 @@ def test_16bit_storage_is_deterministic():
             outs.append(s.get_fields(np.float32))
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("storage", ["f16c", "bf16c"])
+def test_compensated_roundtrip_matches_reference(storage):
+    """set, then get, returns the host encoding of the FP32 values bit for bit."""
+    from paper_2504_09118_amd import Solver
+
+    nx, ny, nz = 11, 9, 7
+    h = [a * np.float32(37.5) for a in ci.random_h(nx, ny, nz, seed=4, dtype=np.float32)]
+    e = [a * np.float32(1e-3) for a in ci.random_e(nx, ny, nz, seed=4, dtype=np.float32)]
+    with Solver(nx, ny, nz, 1.0, S, storage=storage) as s:
+        s.set_fields(e, h)
+        got = s.get_fields()
+    for g, a in zip(got[3:], h):
+        assert np.array_equal(g, comp_store(a, storage))
+    walls = oracle.make_state([comp_store(a, storage) for a in e])[:3]
+    for g, a in zip(got[:3], walls):
+        assert np.array_equal(g, a)
 
 
 def test_bf16_rounding_matches_reference():

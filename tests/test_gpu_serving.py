@@ -52,7 +52,7 @@ def host_random_state(nx, ny, nz, seed, storage):
     return list(e) + list(h)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16", "f16c", "bf16c"])
 def test_init_random_matches_host_generator(storage):
     P = _pkg()
     nx, ny, nz, seed = 37, 20, 29, 0xC0FFEE
