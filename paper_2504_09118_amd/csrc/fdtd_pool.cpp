@@ -127,22 +127,25 @@ struct Req {
     float *fld[2][6];
     float *ce[3], *ch[3];
     void *staging;
-    int cur, zchunk;
+    int cur;
     hipEvent_t done_ev;
     bool ev_live;  // done_ev created and not yet destroyed
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Per-request z-split: a lone small cavity still spreads over a few hundred
-// workgroups; chunks stay >= 48 planes (each chunk recomputes 2*tb-1 planes).
-int request_zchunk(const Geom &g, int tb)
+// z-split of one batched launch. A launch ends with its longest workgroup, so
+// every request is cut into z-chunks of about the same length (kChunk planes;
+// each chunk recomputes 2*tb-1 planes); a launch with fewer than kTargetTiles
+// workgroups halves the length once to fill more CUs. The split never changes
+// a request's bits.
+constexpr int kChunk = 48;
+constexpr int kTargetTiles = 512;
+
+int zsplit(const Geom &g, int len)
 {
-    int kc, ntx, nty, ntiles;
-    fdtd::temporal_tiling(g, tb, 1, &kc, &ntx, &nty, &ntiles);
-    int zc = 1;
-    while ((long long)ntiles * zc < 256 && g.nz / (zc * 2) >= 48) zc *= 2;
-    return zc;
+    const int zc = (g.nz + len / 2) / len;
+    return zc < 1 ? 1 : zc;
 }
 
 bool request_aux(const fdtd_request &r) { return r.eps_r || r.mu_r || r.fields || r.keep; }
@@ -255,7 +258,7 @@ bool admit(fdtd_pool_t p)
         std::lock_guard<std::mutex> lk(p->mu);
         p->seen_epoch = p->epoch;
         for (auto it = p->queue.begin(); it != p->queue.end();) {
-            if ((int)(p->active.size() + admitted.size()) >= p->max_active)
+            if ((int)p->active.size() >= p->max_active)
                 break;
             Req &r = **it;
             size_t off;
@@ -271,7 +274,11 @@ bool admit(fdtd_pool_t p)
             r.t_admit = seconds_since(p->t0);
             admitted.push_back(&r);
             it = p->queue.erase(it);
+            // listed as active in the same critical section that takes it off the queue, so a
+            // waiter never sees it in neither list; only this thread launches, after the init below
+            p->active.push_back(&r);
         }
+        p->peak_active = std::max(p->peak_active, (int)p->active.size());
     }
     for (Req *rp : admitted) {
         Req &r = *rp;
@@ -285,7 +292,6 @@ bool admit(fdtd_pool_t p)
         }
         r.staging = r.aux ? (void *)(b + r.plan.off_staging) : nullptr;
         r.cur = 0;
-        r.zchunk = request_zchunk(r.plan.g, p->tb);
         hipError_t e = init_request(p, r);
         if (e == hipSuccess) {
             e = hipEventCreateWithFlags(&r.done_ev, hipEventDisableTiming);
@@ -295,9 +301,6 @@ bool admit(fdtd_pool_t p)
             fail_pool(p, "admission", e);
             return false;
         }
-        std::lock_guard<std::mutex> lk(p->mu);
-        p->active.push_back(&r);
-        p->peak_active = std::max(p->peak_active, (int)p->active.size());
     }
     return true;
 }
@@ -380,6 +383,13 @@ bool launch_round(fdtd_pool_t p)
         BatchEntry *tab = p->host_tab[slot];
         int ntiles = 0, n = 0;
         double cells = 0;
+        long long tiles_at_chunk = 0;
+        for (Req *r : kv.second) {
+            int kc, ntx, nty, nt;
+            fdtd::temporal_tiling(r->plan.g, ts, zsplit(r->plan.g, kChunk), &kc, &ntx, &nty, &nt);
+            tiles_at_chunk += nt;
+        }
+        const int len = tiles_at_chunk < kTargetTiles ? kChunk / 2 : kChunk;
         for (Req *r : kv.second) {
             BatchEntry &e = tab[n++];
             e.g = r->plan.g;
@@ -393,7 +403,7 @@ bool launch_round(fdtd_pool_t p)
             }
             e.c.ce_s = (float)(r->dt / r->dx);
             e.c.ch_s = (float)(r->dt / r->dx);
-            fdtd::temporal_tiling(r->plan.g, ts, r->zchunk, &e.kchunk, &e.ntx, &e.nty, &e.ntiles);
+            fdtd::temporal_tiling(r->plan.g, ts, zsplit(r->plan.g, len), &e.kchunk, &e.ntx, &e.nty, &e.ntiles);
             e.tile_begin = ntiles;
             ntiles += e.ntiles;
             cells += (double)r->nx * r->ny * r->nz * ts;
