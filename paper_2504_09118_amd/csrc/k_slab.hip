@@ -104,6 +104,9 @@ __device__ __forceinline__ void st1(T *plane, unsigned boff, T x)
 // the same on every path; the wait for the prefetch then never covers stores.
 constexpr unsigned kDrop = 0x80000000u;
 constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
+// cache policy of the stores: non-temporal (the written state is not read again in this
+// sweep), so written lines leave L2 early and the lines of the tiles' shared halos stay
+constexpr int kStoreNT = 2;
 
 template <typename T, int V>
 __device__ __forceinline__ void st_plane(T *plane, unsigned plane_bytes, unsigned boff,
@@ -112,13 +115,13 @@ __device__ __forceinline__ void st_plane(T *plane, unsigned plane_bytes, unsigne
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, (int)plane_bytes, kRawBufferWord3);
     constexpr int bytes = (int)sizeof(T) * V;
     if constexpr (bytes == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, boff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, boff, 0, kStoreNT);
     } else if constexpr (bytes == 8) {
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, boff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, boff, 0, kStoreNT);
     } else {
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, boff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, boff, 0, kStoreNT);
     }
 }
 

@@ -95,6 +95,9 @@ __device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *
 // the same on every path; the wait for the prefetch then never covers stores.
 constexpr unsigned kDrop = 0x80000000u;
 constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data format, no swizzle
+// cache policy of the stores: non-temporal (the written state is not read again in this
+// sweep), so written lines leave L2 early and the lines of the tiles' shared halos stay
+constexpr int kStoreNT = 2;
 
 template <typename S>
 __device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigned boff, char *lo_plane,
@@ -114,20 +117,20 @@ __device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigne
         unsigned short ua, ub;
         __builtin_memcpy(&ua, &a, 2);
         __builtin_memcpy(&ub, &b, 2);
-        __builtin_amdgcn_raw_buffer_store_b32((unsigned)ua | ((unsigned)ub << 16), r, boff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32((unsigned)ua | ((unsigned)ub << 16), r, boff, 0, kStoreNT);
         if constexpr (Store<S>::comp) {
             // residual box: one byte per cell, the same plane layout (a dropped offset stays dropped)
             const __amdgpu_buffer_rsrc_t rq =
                 __builtin_amdgcn_make_buffer_rsrc(lo_plane, 0, (int)(plane_bytes / 2), kRawBufferWord3);
             const unsigned short q = (unsigned short)((unsigned char)qa | ((unsigned)(unsigned char)qb << 8));
-            __builtin_amdgcn_raw_buffer_store_b16(q, rq, boff / 2, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b16(q, rq, boff / 2, 0, kStoreNT);
         }
     } else if constexpr (sizeof(S) == 4) {
         (void)lo_plane;
-        __builtin_amdgcn_raw_buffer_store_b64(x, r, boff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, boff, 0, kStoreNT);
     } else {
         (void)lo_plane;
-        __builtin_amdgcn_raw_buffer_store_b128(x, r, boff, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, boff, 0, kStoreNT);
     }
 }
 
