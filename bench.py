@@ -19,6 +19,7 @@ import hashlib
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -128,16 +129,22 @@ def main() -> int:
     print(f"[bench] kernel={kernel} steps/sweep={steps_per_launch} warmup done", file=sys.stderr, flush=True)
 
     sweeps_before = s.query()["sweeps"]
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # the timed steps run as up to 10 equal repetitions (whole sweeps each, the last one takes
+    # the remainder) with an event between repetitions, so the line also carries mean and spread
+    nrep = max(1, min(10, args.steps // steps_per_launch))
+    chunk = args.steps // nrep // steps_per_launch * steps_per_launch
+    chunks = [chunk] * (nrep - 1) + [args.steps - chunk * (nrep - 1)]
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nrep + 1)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    ev0.record(stream)
-    s.step(args.steps)
-    ev1.record(stream)
+    evs[0].record(stream)
+    for r, c in enumerate(chunks):
+        s.step(c)
+        evs[r + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1)
+    ms = evs[0].elapsed_time(evs[-1])
+    rep_rates = [nx * ny * nz * c / (evs[r].elapsed_time(evs[r + 1]) / 1e3) / 1e9 for r, c in enumerate(chunks)]
     sweeps = s.query()["sweeps"] - sweeps_before
     s_sched = s.schedule
     d = s.diag()
@@ -186,6 +193,9 @@ def main() -> int:
                      "avg_launch_ms": round(avg_launch_s * 1e3, 5),
                      # throughput against the single-step HBM roofline (each step moving b_sweep bytes)
                      "frac_of_single_step_roofline": round(gcells / (HBM_PEAK_GBS / b_sweep), 4)},
+        "repetitions": {"n": nrep, "steps_each": chunks, "gcells_mean": round(statistics.fmean(rep_rates), 3),
+                        "gcells_std": round(statistics.pstdev(rep_rates), 3),
+                        "gcells_min": round(min(rep_rates), 3), "gcells_max": round(max(rep_rates), 3)},
         "wall_s": round(wall, 4),
         "energy_check": {"nonfinite": d["nonfinite"], "max_e_tan": d["max_e_tan"]},
     }
@@ -241,9 +251,18 @@ def cpu_baseline(e32, eps, nx, ny, nz, dx, dt, steps):
     oracle.run(fields, ce, ch, steps)
     secs = time.perf_counter() - t0
     rate = nx * ny * nz * steps / secs / 1e9
+    # the same oracle on one thread, a shorter sample of the same state
+    steps1 = max(1, steps // 30)
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.run(fields, ce, ch, steps1)
+    secs1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
+    rate1 = nx * ny * nz * steps1 / secs1 / 1e9
     return {"value": round(rate, 5), "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"full {nx}x{ny}x{nz} cavity, same inputs, {steps} leapfrog steps in FP64 "
-                      f"({secs:.1f}s)"}
+                      f"({secs:.1f}s); one thread: {steps1} more steps ({secs1:.1f}s)",
+            "value_1thread": round(rate1, 5)}
 
 
 if __name__ == "__main__":

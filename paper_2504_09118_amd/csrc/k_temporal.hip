@@ -105,25 +105,19 @@ __device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigne
 {
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, (int)plane_bytes, kRawBufferWord3);
     if constexpr (sizeof(S) == 2) {
-        S a, b;
-        signed char qa = 0, qb = 0;
+        // both cells rounded by one packed conversion
         if constexpr (Store<S>::comp) {
-            Store<S>::enc(x[0], a, qa);
-            Store<S>::enc(x[1], b, qb);
-        } else {
-            a = Store<S>::narrow(x[0]);
-            b = Store<S>::narrow(x[1]);
-        }
-        unsigned short ua, ub;
-        __builtin_memcpy(&ua, &a, 2);
-        __builtin_memcpy(&ub, &b, 2);
-        __builtin_amdgcn_raw_buffer_store_b32((unsigned)ua | ((unsigned)ub << 16), r, boff, 0, kStoreNT);
-        if constexpr (Store<S>::comp) {
+            unsigned hh;
+            unsigned short q;
+            Store<S>::enc2(x[0], x[1], hh, q);
+            __builtin_amdgcn_raw_buffer_store_b32(hh, r, boff, 0, kStoreNT);
             // residual box: one byte per cell, the same plane layout (a dropped offset stays dropped)
             const __amdgpu_buffer_rsrc_t rq =
                 __builtin_amdgcn_make_buffer_rsrc(lo_plane, 0, (int)(plane_bytes / 2), kRawBufferWord3);
-            const unsigned short q = (unsigned short)((unsigned char)qa | ((unsigned)(unsigned char)qb << 8));
             __builtin_amdgcn_raw_buffer_store_b16(q, rq, boff / 2, 0, kStoreNT);
+        } else {
+            (void)lo_plane;
+            __builtin_amdgcn_raw_buffer_store_b32(Store<S>::pack2(x[0], x[1]), r, boff, 0, kStoreNT);
         }
     } else if constexpr (sizeof(S) == 4) {
         (void)lo_plane;

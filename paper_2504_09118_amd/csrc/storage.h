@@ -28,9 +28,17 @@ __host__ __device__ inline float bf16_to_float(bf16 b)
     return x.f;
 }
 
-// Round to nearest, ties to even; NaN stays a quiet NaN.
+// Round to nearest, ties to even; NaN stays a quiet NaN. On the device this is
+// gfx950's conversion instruction (nearest even under the default rounding mode,
+// FP32 denormals kept); the host form rounds the bits.
 __host__ __device__ inline bf16 float_to_bf16(float f)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const __bf16 h = (__bf16)f;
+    bf16 r;
+    __builtin_memcpy(&r.u, &h, 2);
+    return r;
+#else
     union {
         unsigned int u;
         float f;
@@ -44,6 +52,30 @@ __host__ __device__ inline bf16 float_to_bf16(float f)
     const unsigned int lsb = (x.u >> 16) & 1u;
     r.u = (unsigned short)((x.u + 0x7fffu + lsb) >> 16);
     return r;
+#endif
+}
+
+// Two FP32 values rounded to nearest even and packed as 16-bit values, a in the
+// low half: one packed conversion instruction on gfx950 (v_cvt_pk_f16_f32,
+// v_cvt_pk_bf16_f32).
+typedef float pk_f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 pk_f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 pk_bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline unsigned pack2_f16(float a, float b)
+{
+    const pk_f16x2 h = __builtin_convertvector((pk_f32x2){a, b}, pk_f16x2);
+    unsigned u;
+    __builtin_memcpy(&u, &h, 4);
+    return u;
+}
+
+__device__ inline unsigned pack2_bf16(float a, float b)
+{
+    const pk_bf16x2 h = __builtin_convertvector((pk_f32x2){a, b}, pk_bf16x2);
+    unsigned u;
+    __builtin_memcpy(&u, &h, 4);
+    return u;
 }
 
 // Compensated 16-bit storage: the 16-bit value (array of these) plus, in a
@@ -81,6 +113,7 @@ struct Store<f16> {
     static constexpr bool comp = false;
     __host__ __device__ static C widen(f16 v) { return (float)v; }
     __host__ __device__ static f16 narrow(C v) { return (f16)v; }
+    __device__ static unsigned pack2(C a, C b) { return pack2_f16(a, b); }
 };
 
 template <>
@@ -89,6 +122,7 @@ struct Store<bf16> {
     static constexpr bool comp = false;
     __host__ __device__ static C widen(bf16 v) { return bf16_to_float(v); }
     __host__ __device__ static bf16 narrow(C v) { return float_to_bf16(v); }
+    __device__ static unsigned pack2(C a, C b) { return pack2_bf16(a, b); }
 };
 
 __host__ __device__ inline unsigned f32_bits(float f)
@@ -131,10 +165,28 @@ __host__ __device__ inline float comp_scale_bf16(unsigned short hbits)
     return bits_f32((unsigned)(e - 127 - 7 - 8 + 127) << 23);
 }
 
-__host__ __device__ inline signed char comp_residual(float x, float hi, float scale)
+// 1 / s for the encoder: also a power of two in the normal range (2^2..2^32 for FP16,
+// 2^-113..2^126 for BF16), so r * (1/s) is the same correctly rounded value as r / s
+// without a division sequence.
+__host__ __device__ inline float comp_inv_scale_f16(unsigned short hbits)
 {
-    float q = __builtin_rintf((x - hi) / scale);  // the division is exact: scale is a power of two
-    q = q > 127.0f ? 127.0f : (q < -127.0f ? -127.0f : q);
+    int e = (hbits >> 10) & 0x1f;
+    e = e < 1 ? 1 : e;
+    return bits_f32((unsigned)(15 + 10 + 8 - e + 127) << 23);
+}
+
+__host__ __device__ inline float comp_inv_scale_bf16(unsigned short hbits)
+{
+    int e = (hbits >> 7) & 0xff;
+    e = e < 16 ? 16 : e;
+    return bits_f32((unsigned)(127 + 7 + 8 - e + 127) << 23);
+}
+
+__host__ __device__ inline signed char comp_residual(float x, float hi, float inv_scale)
+{
+    // exact scaling by a power of two; |q| <= 128 for a finite x, so the clamp only folds
+    // the half-ulp case 128 onto 127 (a NaN x gives hi = NaN, whatever q holds)
+    const float q = __builtin_fminf(__builtin_fmaxf(__builtin_rintf((x - hi) * inv_scale), -127.0f), 127.0f);
     return (signed char)(int)q;
 }
 
@@ -155,7 +207,19 @@ struct Store<f16c> {
     __host__ __device__ static void enc(C x, f16c &hi, signed char &q)
     {
         hi.h = (_Float16)x;
-        q = comp_residual(x, (float)hi.h, comp_scale_f16(bits(hi)));
+        q = comp_residual(x, (float)hi.h, comp_inv_scale_f16(bits(hi)));
+    }
+    // two values: the packed 16-bit pair (a low) and the packed residual bytes
+    __device__ static void enc2(C a, C b, unsigned &hh, unsigned short &qq)
+    {
+        hh = pack2_f16(a, b);
+        const unsigned short ua = (unsigned short)(hh & 0xffffu), ub = (unsigned short)(hh >> 16);
+        _Float16 ha, hb;
+        __builtin_memcpy(&ha, &ua, 2);
+        __builtin_memcpy(&hb, &ub, 2);
+        const signed char qa = comp_residual(a, (float)ha, comp_inv_scale_f16(ua));
+        const signed char qb = comp_residual(b, (float)hb, comp_inv_scale_f16(ub));
+        qq = (unsigned short)((unsigned char)qa | ((unsigned)(unsigned char)qb << 8));
     }
 };
 
@@ -170,7 +234,15 @@ struct Store<bf16c> {
     __host__ __device__ static void enc(C x, bf16c &hi, signed char &q)
     {
         hi.u = float_to_bf16(x).u;
-        q = comp_residual(x, bf16_to_float(bf16{hi.u}), comp_scale_bf16(hi.u));
+        q = comp_residual(x, bf16_to_float(bf16{hi.u}), comp_inv_scale_bf16(hi.u));
+    }
+    __device__ static void enc2(C a, C b, unsigned &hh, unsigned short &qq)
+    {
+        hh = pack2_bf16(a, b);
+        const unsigned short ua = (unsigned short)(hh & 0xffffu), ub = (unsigned short)(hh >> 16);
+        const signed char qa = comp_residual(a, bf16_to_float(bf16{ua}), comp_inv_scale_bf16(ua));
+        const signed char qb = comp_residual(b, bf16_to_float(bf16{ub}), comp_inv_scale_bf16(ub));
+        qq = (unsigned short)((unsigned char)qa | ((unsigned)(unsigned char)qb << 8));
     }
 };
 

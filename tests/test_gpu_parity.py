@@ -304,3 +304,46 @@ def test_parity_256_cavity_1000_steps():
         assert oracle.tangential_max(got) == 0.0
     for a, b in zip(results["fused"], results["auto"]):
         assert np.array_equal(a, b)
+
+
+DEGENERATE_DIMS = [(2, 2, 2), (2, 3, 65), (65, 2, 2), (3, 67, 2), (129, 2, 3)]
+SCHEDULES = [("plain", 0), ("fused", 0), ("slab", 0), ("temporal", 1), ("temporal", 2), ("temporal", 3)]
+
+
+@pytest.mark.parametrize("dims", DEGENERATE_DIMS)
+def test_degenerate_grids_every_schedule(dims):
+    """The smallest grids the boundary accepts (two cells on an axis) and one- or two-cell
+    slabs: every schedule matches the oracle and gives the bits of the plain schedule."""
+    nx, ny, nz = dims
+    steps = 25  # a temporal schedule runs whole sweeps plus a single-step remainder
+    eps = ci.uniform_cell_eps(nx, ny, nz, seed=41, lo=1.0, hi=3.0)
+    e = ci.random_e(nx, ny, nz, seed=42, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=43, dtype=np.float32)
+    ref = oracle_reference(nx, ny, nz, e, h, eps, None, steps)
+    outs = {}
+    for kernel, tb in SCHEDULES:
+        got = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel, tb_steps=tb)
+        err = rel_l2(got, ref)
+        assert err < 1e-5, (dims, kernel, tb, err)
+        assert oracle.tangential_max(got) == 0.0
+        outs[(kernel, tb)] = got
+    for key, out in outs.items():
+        for a, b in zip(out, outs[("plain", 0)]):
+            assert np.array_equal(a, b), key
+    got64 = run_gpu(nx, ny, nz, e, h, eps, None, steps, storage="f64")
+    assert rel_l2(got64, oracle_reference(nx, ny, nz, e, h, eps, None, steps, storage=np.float64)) < 1e-13
+
+
+@pytest.mark.parametrize("kernel", ["plain", "slab", "temporal"])
+def test_zero_steps_leave_the_state_unchanged(kernel):
+    nx, ny, nz = 20, 17, 9
+    e = ci.random_e(nx, ny, nz, seed=44, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=45, dtype=np.float32)
+    with _solver(nx, ny, nz, 1.0, S, kernel=kernel) as s:
+        s.set_fields(e, h)
+        before = s.get_fields(np.float32)
+        s.step(0)
+        assert s.steps_done == 0
+        after = s.get_fields(np.float32)
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)

@@ -170,3 +170,45 @@ def test_bf16_rounding_matches_reference():
         got = s.get_fields()
     for g, a in zip(got[3:], h):
         assert np.array_equal(g, round_bf16(a))
+
+
+def crafted_f32(n):
+    """FP32 bit patterns at the rounding edges of both 16-bit formats: exact ties with
+    even and odd kept bits, one ulp either side of a tie, FP32 and FP16 subnormals,
+    values that round to the largest finite value or overflow, zeros of both signs."""
+    rng = np.random.default_rng(77)
+    hi = rng.integers(0, 1 << 16, size=n, dtype=np.uint64)
+    lo = rng.choice(np.array([0x8000, 0x7FFF, 0x8001, 0x0000, 0xFFFF, 0x1000, 0x2000, 0x0FFF, 0x1001],
+                             dtype=np.uint64), size=n)
+    u = (hi << 16) | lo
+    special = np.array([0x00000001, 0x00008000, 0x00018000, 0x007FFFFF, 0x00800000, 0x7F7FFFFF, 0x7F7F8000,
+                        0x7F7F7FFF, 0x80000000, 0x00000000, 0x33800000, 0x33800001, 0x337FFFFF, 0x38800000,
+                        0x387FE000, 0x387FF000, 0x477FE000, 0x477FF000, 0x477FEFFF, 0xC77FF000],
+                       dtype=np.uint64)
+    u[: special.size] = special
+    f = u.astype(np.uint32).view(np.float32)
+    return np.where(np.isfinite(f), f, np.float32(1.5))
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_16bit_rounding_edges_match_reference(storage):
+    """Ties, subnormals and overflow: the device's packed conversions round exactly as the
+    host reference (numpy's nearest-even float16 cast, round_bf16) - set, then get."""
+    import paper_2504_09118_amd as P
+    from paper_2504_09118_amd import Solver
+
+    nx, ny, nz = 13, 11, 9
+    shapes = [tuple(sh) for sh in P.field_shapes(nx, ny, nz)[3:]]
+    vals = crafted_f32(sum(int(np.prod(sh)) for sh in shapes))
+    h, o = [], 0
+    for sh in shapes:
+        m = int(np.prod(sh))
+        h.append(vals[o:o + m].reshape(sh))
+        o += m
+    e = ci.random_e(nx, ny, nz, seed=3, dtype=np.float32)
+    with Solver(nx, ny, nz, 1.0, S, storage=storage) as s:
+        s.set_fields(e, h)
+        got = s.get_fields()
+    for g, a in zip(got[3:], h):
+        ref = round_store(a, storage)
+        assert np.array_equal(g, ref, equal_nan=True)
