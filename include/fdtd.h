@@ -234,8 +234,10 @@ int fdtd_query(fdtd_t h, long long out[8]);
 
 /*
  * Schedule of fdtd_step: which kernel, its steps per sweep, tile shape and
- * z-split. Every schedule gives the same bits for the same storage type, so
- * choosing one changes only speed.
+ * z-split. For FP32 and FP64 storage every schedule gives the same bits, so
+ * choosing one changes only speed. 16-bit storage rounds the state at the end
+ * of every sweep: there the steps per sweep are part of the numerics (the
+ * same tb_steps gives the same bits whatever the kernel's tiling).
  */
 typedef struct {
     int kernel;         /* FDTD_KERNEL_PLAIN .. FDTD_KERNEL_TEMPORAL */
@@ -255,7 +257,8 @@ int fdtd_set_schedule(fdtd_t h, const fdtd_schedule *sched);
 /*
  * Time every built schedule on this solver (its grid, storage and
  * coefficients: tile sizes, steps per sweep and z-split; the search the
- * paper leaves as future work, Sec. 7) for trial_steps steps each (0: 6;
+ * paper leaves as future work, Sec. 7; 16-bit storage keeps its steps per
+ * sweep and searches the tiling only) for trial_steps steps each (0: 6;
  * rounded up to whole sweeps) after one warm-up sweep, and keep the fastest.
  * The state and the step count are restored afterwards (a copy of the six
  * field boxes is held in a temporary device allocation during the call).

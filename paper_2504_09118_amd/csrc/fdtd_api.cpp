@@ -542,13 +542,27 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     h->tvariant = env_int("FDTD_TEMPORAL_VARIANT", 0);
     h->tzchunk = env_int("FDTD_TZCHUNKS", 0);
     if (h->tzchunk <= 0) {
-        // temporal sweeps redo 2*tb-1 planes per z-chunk: keep chunks >= 48 planes
+        // One temporal workgroup per CU, and a workgroup's time is close to proportional to the
+        // planes it marches (its z-chunk plus the 2*tb-1 planes it redoes): pick the split that
+        // minimises waves-of-workgroups x planes per workgroup, chunks of at least 8 planes.
         const int own = fdtd::temporal_own_rows(h->tb, h->tvariant);
         const int w = fdtd::temporal_width(h->tvariant);
         const long long tiles = (long long)((nx + w - 1) / w) * ((ny + own - 1) / own);
-        int zc = 1;
-        while (tiles * zc < 768 && nz / (zc * 2) >= 48) zc *= 2;
-        h->tzchunk = zc;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, o->device) != hipSuccess || cus < 1)
+            cus = 256;
+        long long best = -1;
+        int zc_best = 1;
+        for (int zc = 1; zc <= std::max(1, nz / 8); ++zc) {
+            const long long kc = (nz + zc - 1) / zc, nzc = (nz + kc - 1) / kc;
+            const long long waves = (tiles * nzc + cus - 1) / cus;
+            const long long cost = waves * (kc + 2 * h->tb - 1);
+            if (best < 0 || cost < best) {
+                best = cost;
+                zc_best = zc;
+            }
+        }
+        h->tzchunk = zc_best;
     }
     if (o->stream) {
         h->stream = (hipStream_t)o->stream;
@@ -935,10 +949,17 @@ std::vector<fdtd_schedule> schedule_candidates(fdtd_t h)
             for (int zc : zcs) add(FDTD_KERNEL_SLAB, 1, v, zc);
         }
     }
+    // the temporal default split need not be a power of two: try it too
+    std::vector<int> tzcs = zcs;
+    if (std::find(tzcs.begin(), tzcs.end(), h->tzchunk) == tzcs.end())
+        tzcs.push_back(h->tzchunk);
+    // 16-bit storage rounds the state at the end of every sweep, so the steps per sweep set
+    // the numerics: the search keeps the solver's own tb there and varies only the tiling
+    const int tb_lo = is16(h->storage) ? h->tb : 1, tb_hi = is16(h->storage) ? h->tb : 3;
     if (h->storage != FDTD_F64)
-        for (int tb = 1; tb <= 3; ++tb)
+        for (int tb = tb_lo; tb <= tb_hi; ++tb)
             for (int v = 0; v < 2; ++v)
-                for (int zc : zcs) add(FDTD_KERNEL_TEMPORAL, tb, v, zc);
+                for (int zc : tzcs) add(FDTD_KERNEL_TEMPORAL, tb, v, zc);
     return out;
 }
 
