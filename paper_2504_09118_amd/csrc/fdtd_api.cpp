@@ -253,16 +253,16 @@ hipError_t launch_one(fdtd_t h, int kernel, int ts)
         // 16-bit storage is built for the temporal sweep only (ts = 1 for single steps)
         (void)kernel;
         e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                          h->tzchunk, ts, h->tvariant, h->stream);
+                                          h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores);
     } else {
         if (kernel == FDTD_KERNEL_PLAIN)
             return fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
         if (kernel == FDTD_KERNEL_SLAB)
             e = fdtd::launch_slab_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                          h->zchunk, h->variant, h->stream);
+                                          h->zchunk, h->variant, h->stream, h->nt_stores);
         else if (kernel == FDTD_KERNEL_TEMPORAL)
             e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                              h->tzchunk, ts, h->tvariant, h->stream);
+                                              h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores);
         else
             e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
                                            h->zchunk, h->stream);
@@ -413,6 +413,37 @@ int solver_check(fdtd_t h) { return check(h); }
 int solver_device_fail(fdtd_t h, hipError_t e, const char *what) { return device_fail(h, e, what); }
 }  // namespace fdtd
 
+namespace {
+
+int device_cus(int device)
+{
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+        cus = 256;
+    return cus;
+}
+
+// z-split for a kernel whose workgroup fills a CU and takes time close to proportional to the
+// planes it marches (its z-chunk plus `redo` planes): the chunk count that minimises
+// (waves of workgroups over the CUs) x (planes per workgroup), chunks of >= min_planes.
+int best_zsplit(long long tiles, int nz, int redo, int min_planes, int cus)
+{
+    long long best = -1;
+    int zc_best = 1;
+    for (int zc = 1; zc <= std::max(1, nz / min_planes); ++zc) {
+        const long long kc = (nz + zc - 1) / zc, nzc = (nz + kc - 1) / kc;
+        const long long waves = (tiles * nzc + cus - 1) / cus;
+        const long long cost = waves * (kc + redo);
+        if (best < 0 || cost < best) {
+            best = cost;
+            zc_best = zc;
+        }
+    }
+    return zc_best;
+}
+
+}  // namespace
+
 extern "C" {
 
 int fdtd_opts_default(fdtd_opts *o)
@@ -522,6 +553,19 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     h->ch_arr = mu != nullptr || rect;
     h->ce_s = dt / dx;
     h->ch_s = dt / dx;
+    {
+        // bytes one sweep streams: both state buffers and the coefficient arrays
+        const size_t streamed = 12 * p.fbox_bytes + ((h->ce_arr ? 3 : 0) + (h->ch_arr ? 3 : 0)) * p.cbox_bytes;
+        h->nt_stores = streamed > fdtd::kStreamCacheBytes;
+    }
+    const int slab_v = h->storage == FDTD_F64 ? 3 : h->variant;
+    if (h->zchunk <= 0 && (kern == FDTD_KERNEL_SLAB || kern == FDTD_KERNEL_TEMPORAL) && slab_v == 0) {
+        // the 16-wave slab workgroup (also the single steps of a temporal schedule) fills a CU
+        // like the temporal one (see below); a z-chunk redoes one plane; chunks of >= 4 planes
+        const int own = fdtd::slab_rows(0) - 2, w = fdtd::slab_width(0);
+        const long long tiles = (long long)((nx + w - 1) / w) * ((ny + own - 1) / own);
+        h->zchunk = best_zsplit(tiles, nz, 1, 4, device_cus(o->device));
+    }
     if (h->zchunk <= 0) {
         // split z so the launch has enough workgroups to cover the 256 CUs several times
         long long tiles;
@@ -548,21 +592,7 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         const int own = fdtd::temporal_own_rows(h->tb, h->tvariant);
         const int w = fdtd::temporal_width(h->tvariant);
         const long long tiles = (long long)((nx + w - 1) / w) * ((ny + own - 1) / own);
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, o->device) != hipSuccess || cus < 1)
-            cus = 256;
-        long long best = -1;
-        int zc_best = 1;
-        for (int zc = 1; zc <= std::max(1, nz / 8); ++zc) {
-            const long long kc = (nz + zc - 1) / zc, nzc = (nz + kc - 1) / kc;
-            const long long waves = (tiles * nzc + cus - 1) / cus;
-            const long long cost = waves * (kc + 2 * h->tb - 1);
-            if (best < 0 || cost < best) {
-                best = cost;
-                zc_best = zc;
-            }
-        }
-        h->tzchunk = zc_best;
+        h->tzchunk = best_zsplit(tiles, nz, 2 * h->tb - 1, 8, device_cus(o->device));
     }
     if (o->stream) {
         h->stream = (hipStream_t)o->stream;

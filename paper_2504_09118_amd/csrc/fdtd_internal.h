@@ -70,17 +70,27 @@ hipError_t launch_fused_step(const Geom &g, const Fields<T> &src, const Fields<T
 
 // Slab step (fused sweep with V-wide lanes, prefetch and XCD-aware tiles):
 // reads src, writes dst. variant selects the tile shape (0 = default).
+// nt_stores: store the new state with the non-temporal cache policy (right when
+// the streamed state is larger than the last-level cache; see kStreamCacheBytes).
 template <typename T>
 hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
-                            const Coefs<T> &c, int zchunk, int variant, hipStream_t s);
+                            const Coefs<T> &c, int zchunk, int variant, hipStream_t s, bool nt_stores = true);
 
 // Temporal step: ts (1..3) leapfrog steps in one sweep; reads src, writes dst.
 // Built for FP32, FP16 and BF16 field storage (16-bit fields compute in FP32
 // with FP32 coefficients).
+// nt_stores as for the slab step (honoured for FP32 fields; 16-bit fields always
+// store non-temporally).
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                                 const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant,
-                                hipStream_t s);
+                                hipStream_t s, bool nt_stores = true);
+
+// MI355X's Infinity Cache (256 MB, the last level before HBM). A sweep whose streamed
+// bytes (both state buffers and the coefficient arrays) fit in it keeps the default
+// store policy, so the next sweep reads the state from the cache; larger states store
+// non-temporally, which leaves L2 to the halo lines neighbouring tiles share.
+constexpr size_t kStreamCacheBytes = (size_t)256 << 20;
 int temporal_own_rows(int ts, int variant);
 int temporal_width(int variant);
 

@@ -108,24 +108,24 @@ constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data for
 // sweep), so written lines leave L2 early and the lines of the tiles' shared halos stay
 constexpr int kStoreNT = 2;
 
-template <typename T, int V>
+template <typename T, int V, bool NT>
 __device__ __forceinline__ void st_plane(T *plane, unsigned plane_bytes, unsigned boff,
                                          const typename VecOf<T, V>::type &x)
 {
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, (int)plane_bytes, kRawBufferWord3);
     constexpr int bytes = (int)sizeof(T) * V;
     if constexpr (bytes == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, boff, 0, kStoreNT);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, boff, 0, NT ? kStoreNT : 0);
     } else if constexpr (bytes == 8) {
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, boff, 0, kStoreNT);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, boff, 0, NT ? kStoreNT : 0);
     } else {
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, boff, 0, kStoreNT);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, x), r, boff, 0, NT ? kStoreNT : 0);
     }
 }
 
-template <typename T, int V, int R, bool CE_ARR, bool CH_ARR>
+template <typename T, int V, int R, bool CE_ARR, bool CH_ARR, bool NT>
 __global__ void __launch_bounds__(64 * R)
     k_slab(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles,
                int xcd_remap)
@@ -344,9 +344,9 @@ __global__ void __launch_bounds__(64 * R)
             // unconditional stores (see st_plane): a cell at i >= nx carries its loaded,
             // never-updated value (a wall or padding constant equal in both buffers)
             const unsigned so = hrow && erow && act && own ? off : kDrop;
-            st_plane<T, V>(dst.f[3] + pk, plane_bytes, so, hx);
-            st_plane<T, V>(dst.f[4] + pk, plane_bytes, so, hy);
-            st_plane<T, V>(dst.f[5] + pk, plane_bytes, so, hz);
+            st_plane<T, V, NT>(dst.f[3] + pk, plane_bytes, so, hx);
+            st_plane<T, V, NT>(dst.f[4] + pk, plane_bytes, so, hy);
+            st_plane<T, V, NT>(dst.f[5] + pk, plane_bytes, so, hz);
         }
         __syncthreads();
         // ---------------- E^{n+1} at plane k ----------------
@@ -376,9 +376,9 @@ __global__ void __launch_bounds__(64 * R)
         }
         {
             const unsigned so = erow && act && own ? off : kDrop;
-            st_plane<T, V>(dst.f[0] + pk, plane_bytes, so, ex);
-            st_plane<T, V>(dst.f[1] + pk, plane_bytes, so, ey);
-            st_plane<T, V>(dst.f[2] + pk, plane_bytes, so, ez);
+            st_plane<T, V, NT>(dst.f[0] + pk, plane_bytes, so, ex);
+            st_plane<T, V, NT>(dst.f[1] + pk, plane_bytes, so, ey);
+            st_plane<T, V, NT>(dst.f[2] + pk, plane_bytes, so, ez);
         }
         // ---------------- rotate the pipeline ----------------
         hpx = hx;
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(64 * R)
     }
 }
 
-template <typename T, int V, int R>
+template <typename T, int V, int R, bool NT>
 hipError_t launch_cfg(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c, int zchunk,
                       hipStream_t s)
 {
@@ -426,18 +426,30 @@ hipError_t launch_cfg(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
     dim3 block(64, R), grid(nblocks);
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
     if (cea && cha)
-        hipLaunchKernelGGL((k_slab<T, V, R, true, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+        hipLaunchKernelGGL((k_slab<T, V, R, true, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
                            ntiles, xcd_remap());
     else if (cea)
-        hipLaunchKernelGGL((k_slab<T, V, R, true, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+        hipLaunchKernelGGL((k_slab<T, V, R, true, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
                            ntiles, xcd_remap());
     else if (cha)
-        hipLaunchKernelGGL((k_slab<T, V, R, false, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+        hipLaunchKernelGGL((k_slab<T, V, R, false, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
                            ntiles, xcd_remap());
     else
-        hipLaunchKernelGGL((k_slab<T, V, R, false, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+        hipLaunchKernelGGL((k_slab<T, V, R, false, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
                            ntiles, xcd_remap());
     return hipGetLastError();
+}
+
+template <typename T, bool NT>
+hipError_t launch_variant(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c, int zchunk,
+                          int variant, hipStream_t s)
+{
+    switch (variant) {
+    case 1: return launch_cfg<T, 2, 8, NT>(g, src, dst, c, zchunk, s);
+    case 2: return launch_cfg<T, 1, 16, NT>(g, src, dst, c, zchunk, s);
+    case 3: return launch_cfg<T, 1, 8, NT>(g, src, dst, c, zchunk, s);
+    default: return launch_cfg<T, 2, 16, NT>(g, src, dst, c, zchunk, s);
+    }
 }
 
 }  // namespace
@@ -451,22 +463,18 @@ int slab_width(int variant) { return variant == 2 || variant == 3 ? 64 : 128; }
 
 template <typename T>
 hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c,
-                            int zchunk, int variant, hipStream_t s)
+                            int zchunk, int variant, hipStream_t s, bool nt_stores)
 {
     zchunk = zchunk < 1 ? 1 : zchunk;
     if (sizeof(T) == 8)
         variant = 3;
-    switch (variant) {
-    case 1: return launch_cfg<T, 2, 8>(g, src, dst, c, zchunk, s);
-    case 2: return launch_cfg<T, 1, 16>(g, src, dst, c, zchunk, s);
-    case 3: return launch_cfg<T, 1, 8>(g, src, dst, c, zchunk, s);
-    default: return launch_cfg<T, 2, 16>(g, src, dst, c, zchunk, s);
-    }
+    return nt_stores ? launch_variant<T, true>(g, src, dst, c, zchunk, variant, s)
+                     : launch_variant<T, false>(g, src, dst, c, zchunk, variant, s);
 }
 
 template hipError_t launch_slab_step<float>(const Geom &, const Fields<float> &, const Fields<float> &,
-                                            const Coefs<float> &, int, int, hipStream_t);
+                                            const Coefs<float> &, int, int, hipStream_t, bool);
 template hipError_t launch_slab_step<double>(const Geom &, const Fields<double> &, const Fields<double> &,
-                                             const Coefs<double> &, int, int, hipStream_t);
+                                             const Coefs<double> &, int, int, hipStream_t, bool);
 
 }  // namespace fdtd

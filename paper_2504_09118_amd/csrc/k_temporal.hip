@@ -28,6 +28,8 @@
 // Only the last stage stores, only own cells. Arithmetic per node is
 // curl_update with the operand order of every other schedule: TS sweeps of
 // this kernel equal TS single steps bit for bit.
+#include <type_traits>
+
 #include "fdtd_internal.h"
 #include "storage.h"
 #include "yee_update.h"
@@ -99,10 +101,11 @@ constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data for
 // sweep), so written lines leave L2 early and the lines of the tiles' shared halos stay
 constexpr int kStoreNT = 2;
 
-template <typename S>
+template <typename S, bool NT>
 __device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigned boff, char *lo_plane,
                                          const typename V2<typename Store<S>::C>::type &x)
 {
+    constexpr int kPol = NT ? kStoreNT : 0;
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, (int)plane_bytes, kRawBufferWord3);
     if constexpr (sizeof(S) == 2) {
         // both cells rounded by one packed conversion
@@ -110,21 +113,21 @@ __device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigne
             unsigned hh;
             unsigned short q;
             Store<S>::enc2(x[0], x[1], hh, q);
-            __builtin_amdgcn_raw_buffer_store_b32(hh, r, boff, 0, kStoreNT);
+            __builtin_amdgcn_raw_buffer_store_b32(hh, r, boff, 0, kPol);
             // residual box: one byte per cell, the same plane layout (a dropped offset stays dropped)
             const __amdgpu_buffer_rsrc_t rq =
                 __builtin_amdgcn_make_buffer_rsrc(lo_plane, 0, (int)(plane_bytes / 2), kRawBufferWord3);
-            __builtin_amdgcn_raw_buffer_store_b16(q, rq, boff / 2, 0, kStoreNT);
+            __builtin_amdgcn_raw_buffer_store_b16(q, rq, boff / 2, 0, kPol);
         } else {
             (void)lo_plane;
-            __builtin_amdgcn_raw_buffer_store_b32(Store<S>::pack2(x[0], x[1]), r, boff, 0, kStoreNT);
+            __builtin_amdgcn_raw_buffer_store_b32(Store<S>::pack2(x[0], x[1]), r, boff, 0, kPol);
         }
     } else if constexpr (sizeof(S) == 4) {
         (void)lo_plane;
-        __builtin_amdgcn_raw_buffer_store_b64(x, r, boff, 0, kStoreNT);
+        __builtin_amdgcn_raw_buffer_store_b64(x, r, boff, 0, kPol);
     } else {
         (void)lo_plane;
-        __builtin_amdgcn_raw_buffer_store_b128(x, r, boff, 0, kStoreNT);
+        __builtin_amdgcn_raw_buffer_store_b128(x, r, boff, 0, kPol);
     }
 }
 
@@ -146,7 +149,7 @@ struct TShape {
 
 // One workgroup's tile: columns [64*tile_x ...), own rows starting at
 // tile_y * (R - 2 TS), planes [zc * kchunk, ...).
-template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR>
+template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR, bool NT>
 __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &src, const Fields<S> &dst,
                                               const Coefs<typename Store<S>::C> &c, int kchunk, int tile_x,
                                               int tile_y, int zc)
@@ -421,12 +424,12 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                 const bool wr = livep && own && pp >= kb;
                 const unsigned so = wr ? offs : kDrop;
                 const long long pk = (long long)(pp > 0 ? pp : 0) * P;
-                st_plane(dst.f[0] + pk, plane_bytes, so, lq(dst.f[0], pk), ex);
-                st_plane(dst.f[1] + pk, plane_bytes, so, lq(dst.f[1], pk), ey);
-                st_plane(dst.f[2] + pk, plane_bytes, so, lq(dst.f[2], pk), ez);
-                st_plane(dst.f[3] + pk, plane_bytes, so, lq(dst.f[3], pk), hout[sp][0]);
-                st_plane(dst.f[4] + pk, plane_bytes, so, lq(dst.f[4], pk), hout[sp][1]);
-                st_plane(dst.f[5] + pk, plane_bytes, so, lq(dst.f[5], pk), hout[sp][2]);
+                st_plane<S, NT>(dst.f[0] + pk, plane_bytes, so, lq(dst.f[0], pk), ex);
+                st_plane<S, NT>(dst.f[1] + pk, plane_bytes, so, lq(dst.f[1], pk), ey);
+                st_plane<S, NT>(dst.f[2] + pk, plane_bytes, so, lq(dst.f[2], pk), ez);
+                st_plane<S, NT>(dst.f[3] + pk, plane_bytes, so, lq(dst.f[3], pk), hout[sp][0]);
+                st_plane<S, NT>(dst.f[4] + pk, plane_bytes, so, lq(dst.f[4], pk), hout[sp][1]);
+                st_plane<S, NT>(dst.f[5] + pk, plane_bytes, so, lq(dst.f[5], pk), hout[sp][2]);
             }
             eout[sp][0] = ex;
             eout[sp][1] = ey;
@@ -470,7 +473,7 @@ __device__ __forceinline__ int tile_of_block(int ntiles, int xcd_remap)
     return xcd_remap ? (b % kXcds) * nper + b / kXcds : b;
 }
 
-template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR>
+template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR, bool NT>
 __global__ void __launch_bounds__(1024)
     k_temporal(Geom g, Fields<S> src, Fields<S> dst, Coefs<typename Store<S>::C> c, int kchunk, int ntx, int nty,
                int ntiles, int xcd_remap)
@@ -478,7 +481,7 @@ __global__ void __launch_bounds__(1024)
     const int t = tile_of_block(ntiles, xcd_remap);
     if (t >= ntiles)
         return;  // the whole workgroup leaves before any barrier
-    temporal_tile<S, TS, RPW, CE_ARR, CH_ARR>(g, src, dst, c, kchunk, t % ntx, (t / ntx) % nty, t / (ntx * nty));
+    temporal_tile<S, TS, RPW, CE_ARR, CH_ARR, NT>(g, src, dst, c, kchunk, t % ntx, (t / ntx) % nty, t / (ntx * nty));
 }
 
 // One launch over the tiles of several cavities (continuous batching): the
@@ -502,11 +505,11 @@ __global__ void __launch_bounds__(1024)
     }
     const BatchEntry e = table[lo];
     const int u = t - e.tile_begin;
-    temporal_tile<float, TS, 2, CE_ARR, CH_ARR>(e.g, e.src, e.dst, e.c, e.kchunk, u % e.ntx, (u / e.ntx) % e.nty,
+    temporal_tile<float, TS, 2, CE_ARR, CH_ARR, true>(e.g, e.src, e.dst, e.c, e.kchunk, u % e.ntx, (u / e.ntx) % e.nty,
                                                 u / (e.ntx * e.nty));
 }
 
-template <typename T, int TS, int RPW>
+template <typename T, int TS, int RPW, bool NT>
 hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                      const Coefs<typename Store<T>::C> &c, int zchunk, hipStream_t s)
 {
@@ -520,18 +523,38 @@ hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
     dim3 block(64, 16), grid(nblocks);
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
     if (cea && cha)
-        hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
+        hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
                            ntiles, xcd_remap());
     else if (cea)
-        hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
+        hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
                            nty, ntiles, xcd_remap());
     else if (cha)
-        hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, true>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
+        hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
                            nty, ntiles, xcd_remap());
     else
-        hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, false>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
+        hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
                            nty, ntiles, xcd_remap());
     return hipGetLastError();
+}
+
+template <typename T, bool NT>
+hipError_t launch_shape(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
+                        const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant, hipStream_t s)
+{
+    if (variant == 1) {
+        switch (ts) {
+        case 1: return launch_ts<T, 1, 1, NT>(g, src, dst, c, zchunk, s);
+        case 2: return launch_ts<T, 2, 1, NT>(g, src, dst, c, zchunk, s);
+        case 3: return launch_ts<T, 3, 1, NT>(g, src, dst, c, zchunk, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (ts) {
+    case 1: return launch_ts<T, 1, 2, NT>(g, src, dst, c, zchunk, s);
+    case 2: return launch_ts<T, 2, 2, NT>(g, src, dst, c, zchunk, s);
+    case 3: return launch_ts<T, 3, 2, NT>(g, src, dst, c, zchunk, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -586,35 +609,28 @@ hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, 
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                                 const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant,
-                                hipStream_t s)
+                                hipStream_t s, bool nt_stores)
 {
     zchunk = zchunk < 1 ? 1 : zchunk;
-    if (variant == 1) {
-        switch (ts) {
-        case 1: return launch_ts<T, 1, 1>(g, src, dst, c, zchunk, s);
-        case 2: return launch_ts<T, 2, 1>(g, src, dst, c, zchunk, s);
-        case 3: return launch_ts<T, 3, 1>(g, src, dst, c, zchunk, s);
-        default: return hipErrorInvalidValue;
-        }
-    }
-    switch (ts) {
-    case 1: return launch_ts<T, 1, 2>(g, src, dst, c, zchunk, s);
-    case 2: return launch_ts<T, 2, 2>(g, src, dst, c, zchunk, s);
-    case 3: return launch_ts<T, 3, 2>(g, src, dst, c, zchunk, s);
-    default: return hipErrorInvalidValue;
-    }
+    // the default-policy stores are built for FP32 fields only (the small, cache-resident
+    // states that profit from them are FP32 in practice)
+    if constexpr (std::is_same<T, float>::value)
+        if (!nt_stores)
+            return launch_shape<T, false>(g, src, dst, c, zchunk, ts, variant, s);
+    (void)nt_stores;
+    return launch_shape<T, true>(g, src, dst, c, zchunk, ts, variant, s);
 }
 
 template hipError_t launch_temporal_step<float>(const Geom &, const Fields<float> &, const Fields<float> &,
-                                                const Coefs<float> &, int, int, int, hipStream_t);
+                                                const Coefs<float> &, int, int, int, hipStream_t, bool);
 template hipError_t launch_temporal_step<f16>(const Geom &, const Fields<f16> &, const Fields<f16> &,
-                                              const Coefs<float> &, int, int, int, hipStream_t);
+                                              const Coefs<float> &, int, int, int, hipStream_t, bool);
 template hipError_t launch_temporal_step<bf16>(const Geom &, const Fields<bf16> &, const Fields<bf16> &,
-                                               const Coefs<float> &, int, int, int, hipStream_t);
+                                               const Coefs<float> &, int, int, int, hipStream_t, bool);
 template hipError_t launch_temporal_step<f16c>(const Geom &, const Fields<f16c> &, const Fields<f16c> &,
-                                               const Coefs<float> &, int, int, int, hipStream_t);
+                                               const Coefs<float> &, int, int, int, hipStream_t, bool);
 template hipError_t launch_temporal_step<bf16c>(const Geom &, const Fields<bf16c> &, const Fields<bf16c> &,
-                                                const Coefs<float> &, int, int, int, hipStream_t);
+                                                const Coefs<float> &, int, int, int, hipStream_t, bool);
 
 }  // namespace fdtd
 
@@ -623,7 +639,7 @@ namespace fdtd {
 // FP64 storage has no temporal kernel (its LDS tiles would not fit); create rejects it.
 template <>
 hipError_t launch_temporal_step<double>(const Geom &, const Fields<double> &, const Fields<double> &,
-                                        const Coefs<double> &, int, int, int, hipStream_t)
+                                        const Coefs<double> &, int, int, int, hipStream_t, bool)
 {
     return hipErrorNotSupported;
 }

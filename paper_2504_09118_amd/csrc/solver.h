@@ -27,6 +27,7 @@ struct fdtd_solver {
     void *fld[2][6];
     void *ce[3], *ch[3];
     bool ce_arr, ch_arr;
+    bool nt_stores;  // sweeps store non-temporally (streamed bytes exceed the last-level cache)
     double ce_s, ch_s;
     void *staging;
     double *diag;
