@@ -319,8 +319,9 @@ int fdtd_adjoint_forward(fdtd_adjoint_t adj, double *J);
  * Reverse pass of the last forward: grad_eps receives dJ/d eps_r per cell
  * (host, nx*ny*nz doubles, x-fastest). lam0, if not NULL, receives dJ/dE^0
  * (three host arrays in the Ex, Ey, Ez host layout, lam0_dtype FDTD_F32 or
- * FDTD_F64). The solver's state afterwards is that of the first recomputed
- * segment's end (not E^N). Waits.
+ * FDTD_F64). The solver's state afterwards is the forward's starting state
+ * (E^0, H^{-1/2}; the recompute borrows its buffers); its step count is left
+ * as the forward left it. Waits.
  */
 int fdtd_adjoint_backward(fdtd_adjoint_t adj, double *grad_eps, void *const lam0[3], int lam0_dtype);
 

@@ -4,8 +4,9 @@
 // Forward: N single leapfrog steps of the solver, each followed by the point
 // source and the probe reads; the state (E^n, H^{n-1/2}) is copied to a
 // checkpoint every K steps. Backward: for each segment of K steps, last one
-// first, the segment is recomputed from its checkpoint keeping every
-// H^{n+1/2}, then walked in reverse with the adjoint sweeps. Device memory:
+// first, the segment is recomputed from its checkpoint with every H^{n+1/2}
+// written straight into a history slot, then walked in reverse with the
+// adjoint sweeps. Device memory:
 // ceil(N/K) checkpoints of six boxes, K history slots of three H boxes, the
 // adjoint fields (six boxes), FP64 dJ/dCe (three boxes) and the FP64 cell
 // gradient.
@@ -188,24 +189,42 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
         e = fdtd::launch_adj_probe<T>(adj, a->np, a->d_pf, a->d_po, a->d_rec + (size_t)a->N * a->np, s->stream);
     if (e != hipSuccess)
         return fdtd::solver_device_fail(s, e, "adjoint setup");
+    // The recompute writes each H^{n+1/2} straight into its history slot: single steps of the
+    // slab sweep (the bits of every schedule) with the slot as the H output and the solver's
+    // two E buffers alternating. Cells no sweep writes (wall-normal H, padding) hold the same
+    // values in every state, so the slots take them once, from the first checkpoint.
+    const int nslots = (int)std::min<long long>(a->K, a->N);
+    for (int q = 0; q < nslots && e == hipSuccess; ++q)
+        for (int f = 0; f < 3 && e == hipSuccess; ++f)
+            e = hipMemcpyAsync(a->hist + ((size_t)q * 3 + f) * a->fbox, a->ckpt + (size_t)(3 + f) * a->fbox, a->fbox,
+                               hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess)
+        return fdtd::solver_device_fail(s, e, "history setup");
+    auto slot_h = [&](long long q, int f) { return (T *)(a->hist + ((size_t)q * 3 + f) * a->fbox + a->guard); };
     for (int seg = a->nseg - 1; seg >= 0; --seg) {
         const long long n0 = (long long)seg * a->K, n1 = std::min(a->N, n0 + a->K);
         if ((e = copy_state(a, a->ckpt + (size_t)seg * 6 * a->fbox, true)) != hipSuccess)
             return fdtd::solver_device_fail(s, e, "restore checkpoint");
         for (long long n = n0; n < n1; ++n) {
-            if (int st = driven_step<T>(a, n, nullptr))
-                return st;
-            char *slot = a->hist + (size_t)(n - n0) * 3 * a->fbox;
-            for (int q = 0; q < 3 && e == hipSuccess; ++q)
-                e = hipMemcpyAsync(slot + (size_t)q * a->fbox, box_of(a, s->fld[s->cur][3 + q]), a->fbox,
-                                   hipMemcpyDeviceToDevice, s->stream);
+            const long long q = n - n0;
+            const int ein = (int)(q & 1) ? 1 - s->cur : s->cur;
+            Fields<T> src, dst;
+            for (int f = 0; f < 3; ++f) {
+                src.f[f] = (T *)s->fld[ein][f];
+                dst.f[f] = (T *)s->fld[1 - ein][f];
+                src.f[3 + f] = q == 0 ? (T *)s->fld[s->cur][3 + f] : slot_h(q - 1, f);
+                dst.f[3 + f] = slot_h(q, f);
+            }
+            e = fdtd::launch_slab_step<T>(g, src, dst, c, s->zchunk, s->variant, s->stream, s->nt_stores);
+            if (e == hipSuccess)
+                e = fdtd::launch_source_probe<T>(dst, a->sf, a->so, a->sf >= 0 ? a->wave[n] : 0.0, 0, a->d_pf,
+                                                 a->d_po, nullptr, a->d_J, s->stream);
             if (e != hipSuccess)
-                return fdtd::solver_device_fail(s, e, "history copy");
+                return fdtd::solver_device_fail(s, e, "recompute step");
         }
         for (long long n = n1 - 1; n >= n0; --n) {
-            char *slot = a->hist + (size_t)(n - n0) * 3 * a->fbox;
             const T *h[3];
-            for (int q = 0; q < 3; ++q) h[q] = (const T *)(slot + (size_t)q * a->fbox + a->guard);
+            for (int f = 0; f < 3; ++f) h[f] = slot_h(n - n0, f);
             e = fdtd::launch_adj_step<T>(g, adj, c, h, a->gce, s->stream);
             if (e == hipSuccess && n >= 1)
                 e = fdtd::launch_adj_probe<T>(adj, a->np, a->d_pf, a->d_po, a->d_rec + (size_t)n * a->np,
@@ -214,7 +233,10 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
                 return fdtd::solver_device_fail(s, e, "adjoint step");
         }
     }
-    e = fdtd::launch_grad_eps<T>(g, c, a->gce, s->dx / s->dt, a->d_grad, s->stream);
+    // the solver leaves with the forward's starting state (the recompute used its buffers)
+    e = copy_state(a, a->ckpt, true);
+    if (e == hipSuccess)
+        e = fdtd::launch_grad_eps<T>(g, c, a->gce, s->dx / s->dt, a->d_grad, s->stream);
     const size_t ncell = (size_t)s->nx * s->ny * s->nz;
     if (e == hipSuccess)
         e = hipMemcpyAsync(grad, a->d_grad, ncell * sizeof(double), hipMemcpyDeviceToHost, s->stream);

@@ -177,3 +177,22 @@ def test_probe_objective_autograd():
     fd = (jp - jm) / (2 * t)
     dot = float(np.sum(g * d))
     assert abs(fd - dot) <= 1e-6 * abs(dot)
+
+
+def test_backward_leaves_the_start_state():
+    """After backward the solver holds (E^0, H^{-1/2}) again, so a second forward and
+    backward repeat J and the gradient bit for bit."""
+    P, A = _pkg()
+    n, eps, src, probes, wave, e0 = problem24(60)
+    with P.Solver(n, n, n, 1.0, S, eps_r=eps) as s:
+        s.set_fields(e0)
+        start = s.get_fields(np.float32)
+        with A.Adjoint(s, src, wave, probes, len(wave), checkpoint_every=7) as a:
+            j1 = a.forward()
+            g1 = a.backward()
+            for x, y in zip(s.get_fields(np.float32), start):
+                assert np.array_equal(x, y)
+            j2 = a.forward()
+            g2 = a.backward()
+    assert j1 == j2
+    assert np.array_equal(g1, g2)
