@@ -148,7 +148,9 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
  * Create a solver for an nx*ny*nz-cell PEC cavity with cubic cells of size dx
  * and time step dt, and enqueue the coefficient precompute on its stream.
  * Fields start at zero.
- * Checks: nx, ny, nz >= 2; dx, dt finite and > 0; every material value
+ * Checks: nx, ny, nz >= 2; nx*ny*nz <= 2^33; one padded x-y plane
+ * (round_up(nx+1, 64) * (ny+1) values) below 2^31 bytes (FDTD_E_ARG);
+ * dx, dt finite and > 0; every material value
  * finite and > 0; the Courant limit dt*sqrt(3)/dx < sqrt(min eps_r * min mu_r)
  * (FDTD_E_CFL); arena large enough (FDTD_E_NOMEM). Host arrays in coef are
  * read during the call only. The arena, if given, is borrowed until

@@ -498,6 +498,15 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         return fail(FDTD_E_UNSUPPORTED, "16-bit storage is built for the temporal kernel only");
     if (kern == FDTD_KERNEL_TEMPORAL && (o->tb_steps < 0 || o->tb_steps > 3))
         return fail(FDTD_E_ARG, "tb_steps must be 1..3 (0: default 3), got %d", o->tb_steps);
+    {
+        // the sweeps address one padded x-y plane with 32-bit byte offsets and mark a dropped
+        // access with an offset of 2^31, so a plane must stay below 2^31 bytes
+        const long long px = ((long long)nx + 1 + 63) / 64 * 64;
+        const long long esz = o->storage == FDTD_F64 ? 8 : o->storage == FDTD_F32 ? 4 : 2;
+        if (px * (ny + 1) * esz >= (1LL << 31))
+            return fail(FDTD_E_ARG, "x-y plane of %lld bytes: planes must stay below 2^31 bytes",
+                        px * (ny + 1) * esz);
+    }
     if (o->arena && o->arena_bytes == 0)
         return fail(FDTD_E_ARG, "arena given with arena_bytes = 0");
     if (!(o->dy == 0.0 || finite_pos(o->dy)) || !(o->dz == 0.0 || finite_pos(o->dz)))

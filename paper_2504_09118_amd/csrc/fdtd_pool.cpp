@@ -664,6 +664,8 @@ int fdtd_pool_submit(fdtd_pool_t p, const fdtd_request *r, long long *id)
         return pfail(FDTD_E_ARG, "dims must be >= 2 (got %d %d %d)", r->nx, r->ny, r->nz);
     if ((long long)r->nx * r->ny * r->nz > (1LL << 31))
         return pfail(FDTD_E_ARG, "request grid too large");
+    if (((long long)r->nx + 1 + 63) / 64 * 64 * (r->ny + 1) * 4 >= (1LL << 31))
+        return pfail(FDTD_E_ARG, "request x-y plane too large (planes must stay below 2^31 bytes)");
     if (!finite_pos(r->dx) || !finite_pos(r->dt))
         return pfail(FDTD_E_ARG, "dx and dt must be finite and > 0 (got %g, %g)", r->dx, r->dt);
     if (r->steps < 0)

@@ -131,6 +131,46 @@ __device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigne
     }
 }
 
+// Buffer load of two field cells of storage type S (compute type out) with the plane as the
+// buffer's range: an offset at or past nrec (kDrop for a lane outside the domain, or nrec = 0
+// for a plane past the chunk) reads zeros. The prefetch loads every plane this way, so it
+// needs neither a branch nor registers cleared ahead of the loads.
+template <typename S>
+__device__ __forceinline__ typename V2<typename Store<S>::C>::type ldb(const S *plane, unsigned nrec, unsigned boff,
+                                                                       const char *lo_plane)
+{
+    using C = typename Store<S>::C;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void *)plane, 0, (int)nrec, kRawBufferWord3);
+    if constexpr (sizeof(S) == 2) {
+        const unsigned u = __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0);
+        const unsigned short ua = (unsigned short)(u & 0xffffu), ub = (unsigned short)(u >> 16);
+        S a, b;
+        __builtin_memcpy(&a, &ua, 2);
+        __builtin_memcpy(&b, &ub, 2);
+        typename V2<C>::type out;
+        if constexpr (Store<S>::comp) {
+            // residual plane: one byte per cell (a dropped offset stays dropped at half)
+            const __amdgpu_buffer_rsrc_t rq =
+                __builtin_amdgcn_make_buffer_rsrc((void *)lo_plane, 0, (int)(nrec / 2), kRawBufferWord3);
+            const unsigned short q = __builtin_amdgcn_raw_buffer_load_b16(rq, boff / 2, 0, 0);
+            out[0] = Store<S>::dec(a, (signed char)(q & 0xff));
+            out[1] = Store<S>::dec(b, (signed char)(q >> 8));
+        } else {
+            out[0] = Store<S>::widen(a);
+            out[1] = Store<S>::widen(b);
+        }
+        return out;
+    } else if constexpr (sizeof(S) == 4) {
+        (void)lo_plane;
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(typename V2<C>::type, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+    } else {
+        (void)lo_plane;
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        return __builtin_bit_cast(typename V2<C>::type, __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0));
+    }
+}
+
 // Workgroup shape of the temporal sweep: 16 waves; RPW rows per wave
 // (64/RPW lanes per row, 2 cells per lane); the last NHW waves hold the
 // x-halo vectors of all rows.
@@ -267,30 +307,29 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     // compiler's conservative merge at the loop head makes every plane wait for its own prefetch
     __builtin_amdgcn_s_waitcnt(0x0F70);
     const unsigned plane_bytes = (unsigned)(P * (long long)sizeof(S));
+    const unsigned cplane_bytes = (unsigned)(P * (long long)sizeof(T));
+    const unsigned lfo = act ? offs : kDrop, lco = act ? offc : kDrop;  // prefetch load offsets
 
     for (int k = k0; k <= kend; ++k) {
         // ---------------- prefetch stage-1 inputs of plane k+1 ----------------
-        vec pE[3] = {zero, zero, zero}, pH[3] = {zero, zero, zero};
-        vec pCe[3] = {(vec)c.ce_s, (vec)c.ce_s, (vec)c.ce_s}, pCh[3] = {(vec)c.ch_s, (vec)c.ch_s, (vec)c.ch_s};
-        if (act && k + 1 <= kend && k + 1 < nz) {
-            const long long pk1 = (long long)(k + 1) * P;
-            if (k + 2 < nz) {
-                pE[0] = ldf(Ex + pk1 + P, offs, lp(Ex, pk1 + P));
-                pE[1] = ldf(Ey + pk1 + P, offs, lp(Ey, pk1 + P));
-                pE[2] = ldf(Ez + pk1 + P, offs, lp(Ez, pk1 + P));
-            }
-            pH[0] = ldf(Hx + pk1, offs, lp(Hx, pk1));
-            pH[1] = ldf(Hy + pk1, offs, lp(Hy, pk1));
-            pH[2] = ldf(Hz + pk1, offs, lp(Hz, pk1));
-            if (CE_ARR) {
-                pCe[0] = ld2(c.ce[0] + pk1, offc);
-                pCe[1] = ld2(c.ce[1] + pk1, offc);
-                pCe[2] = ld2(c.ce[2] + pk1, offc);
-            }
-            if (CH_ARR) {
-                pCh[0] = ld2(c.ch[0] + pk1, offc);
-                pCh[1] = ld2(c.ch[1] + pk1, offc);
-                pCh[2] = ld2(c.ch[2] + pk1, offc);
+        // (planes past the chunk or the domain, and lanes outside it, read zeros)
+        vec pE[3], pH[3], pCe[3], pCh[3];
+        {
+            const bool pv = k + 1 <= kend && k + 1 < nz;
+            const bool pv2 = pv && k + 2 < nz;
+            const long long pk1 = pv ? (long long)(k + 1) * P : 0;
+            const long long pk2 = pv2 ? pk1 + P : 0;
+            const unsigned n1 = pv ? plane_bytes : 0u, n2 = pv2 ? plane_bytes : 0u, nc = pv ? cplane_bytes : 0u;
+            pE[0] = ldb(Ex + pk2, n2, lfo, lp(Ex, pk2));
+            pE[1] = ldb(Ey + pk2, n2, lfo, lp(Ey, pk2));
+            pE[2] = ldb(Ez + pk2, n2, lfo, lp(Ez, pk2));
+            pH[0] = ldb(Hx + pk1, n1, lfo, lp(Hx, pk1));
+            pH[1] = ldb(Hy + pk1, n1, lfo, lp(Hy, pk1));
+            pH[2] = ldb(Hz + pk1, n1, lfo, lp(Hz, pk1));
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                pCe[q] = CE_ARR ? ldb<T>(c.ce[q] + pk1, nc, lco, nullptr) : (vec)c.ce_s;
+                pCh[q] = CH_ARR ? ldb<T>(c.ch[q] + pk1, nc, lco, nullptr) : (vec)c.ch_s;
             }
         }
         // ---------------- stage the E input of every stage ----------------

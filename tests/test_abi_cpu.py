@@ -229,3 +229,11 @@ def test_rectangular_cells_courant_and_arguments():
     assert create(0.1, float("nan"), 0.0) == F.E_ARG
     # rectangular cells always carry per-node coefficient arrays
     assert F.required_bytes(64, 48, 40, dy=0.5) >= F.required_bytes(64, 48, 40, eps_r=True, mu_r=True)
+
+
+def test_create_rejects_oversized_planes():
+    # 24000 x 24000 cells, 2 planes deep: few enough cells, but one padded FP32 x-y plane
+    # (24064 x 24001 x 4 B) reaches 2^31 bytes
+    st, h = _create(24000, 24000, 2)
+    assert st == F.E_ARG and not h.value
+    assert b"plane" in F.load_library().fdtd_last_error()
