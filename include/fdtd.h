@@ -155,6 +155,11 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
  * (FDTD_E_CFL); arena large enough (FDTD_E_NOMEM). Host arrays in coef are
  * read during the call only. The arena, if given, is borrowed until
  * fdtd_destroy and must stay allocated. *out is set only on FDTD_OK.
+ * Environment overrides read here (tuning and test aids; none changes the
+ * bits): FDTD_ZCHUNKS and FDTD_SLAB_VARIANT (fused / slab z-split and tile
+ * shape), FDTD_TZCHUNKS and FDTD_TEMPORAL_VARIANT (temporal sweep),
+ * FDTD_NT_STORES = 0 / 1 (store policy; default: non-temporal when one sweep
+ * streams more than 256 MB).
  */
 int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *coef,
                 const fdtd_opts *opts, fdtd_t *out);

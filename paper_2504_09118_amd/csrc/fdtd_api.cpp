@@ -566,6 +566,9 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         // bytes one sweep streams: both state buffers and the coefficient arrays
         const size_t streamed = 12 * p.fbox_bytes + ((h->ce_arr ? 3 : 0) + (h->ch_arr ? 3 : 0)) * p.cbox_bytes;
         h->nt_stores = streamed > fdtd::kStreamCacheBytes;
+        const int force = env_int("FDTD_NT_STORES", -1);  // 0 / 1 overrides the size rule
+        if (force == 0 || force == 1)
+            h->nt_stores = force == 1;
     }
     const int slab_v = h->storage == FDTD_F64 ? 3 : h->variant;
     if (h->zchunk <= 0 && (kern == FDTD_KERNEL_SLAB || kern == FDTD_KERNEL_TEMPORAL) && slab_v == 0) {

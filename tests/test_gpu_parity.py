@@ -347,3 +347,19 @@ def test_zero_steps_leave_the_state_unchanged(kernel):
         after = s.get_fields(np.float32)
     for a, b in zip(before, after):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("kernel,tb", [("slab", 0), ("temporal", 3), ("temporal", 1)])
+def test_store_policy_gives_the_same_bits(monkeypatch, kernel, tb):
+    """The sweeps are built with default and non-temporal store policies (chosen by state
+    size); both give the same bits."""
+    nx, ny, nz, steps = 70, 19, 37, 31
+    eps = ci.sphere_eps(nx, ny, nz, seed=35, nspheres=6)
+    e = ci.random_e(nx, ny, nz, seed=13, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=14, dtype=np.float32)
+    outs = []
+    for pol in ("0", "1"):
+        monkeypatch.setenv("FDTD_NT_STORES", pol)
+        outs.append(run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel, tb_steps=tb))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
