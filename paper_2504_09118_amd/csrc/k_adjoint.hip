@@ -23,11 +23,29 @@ namespace {
 
 constexpr int kBX = 64, kBY = 4;
 
+constexpr int kProbeBlock = 256;
+
+// Point source and probe reads of one driven step, one workgroup: thread 0 adds w to the
+// source node; probe p is read by thread p (mod the block) in parallel, a probe on the source
+// node adding w itself with the same rounding as the stored value (the source store may land
+// later); thread 0 then sums the squares in probe order, so J has the bits of a serial loop.
 template <typename T>
-__global__ void k_source_probe(Fields<T> f, int sf, long long so, double w, int np, const int *__restrict__ pf,
-                               const long long *__restrict__ po, double *rec_row, double *J)
+__global__ void __launch_bounds__(kProbeBlock) k_source_probe(Fields<T> f, int sf, long long so, double w, int np,
+                                                              const int *__restrict__ pf,
+                                                              const long long *__restrict__ po, double *rec_row,
+                                                              double *J)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
+    const int t = threadIdx.x;
+    if (rec_row) {
+        for (int p = t; p < np; p += kProbeBlock) {
+            T v = f.f[pf[p]][po[p]];
+            if (pf[p] == sf && po[p] == so)
+                v = v + (T)w;
+            rec_row[p] = (double)v;
+        }
+    }
+    __syncthreads();
+    if (t != 0)
         return;
     if (sf >= 0)
         f.f[sf][so] = f.f[sf][so] + (T)w;
@@ -35,20 +53,34 @@ __global__ void k_source_probe(Fields<T> f, int sf, long long so, double w, int 
         return;
     double acc = 0.0;
     for (int p = 0; p < np; ++p) {
-        const double v = (double)f.f[pf[p]][po[p]];
-        rec_row[p] = v;
+        const double v = rec_row[p];
         acc += v * v;
     }
     *J += acc;
 }
 
+// lam += 2 E^n at the probes. Thread p handles probe p (mod the block) unless an earlier
+// probe names the same node; the first one adds the contributions of all its duplicates in
+// probe order, as a serial loop would.
 template <typename T>
-__global__ void k_adj_probe(Fields<T> lam, int np, const int *__restrict__ pf, const long long *__restrict__ po,
-                            const double *__restrict__ rec_row)
+__global__ void __launch_bounds__(kProbeBlock) k_adj_probe(Fields<T> lam, int np, const int *__restrict__ pf,
+                                                           const long long *__restrict__ po,
+                                                           const double *__restrict__ rec_row)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
-        return;
-    for (int p = 0; p < np; ++p) lam.f[pf[p]][po[p]] = lam.f[pf[p]][po[p]] + (T)(2.0 * rec_row[p]);
+    for (int p = threadIdx.x; p < np; p += kProbeBlock) {
+        const int fp = pf[p];
+        const long long op = po[p];
+        bool first = true;
+        for (int q = 0; q < p && first; ++q)
+            first = !(pf[q] == fp && po[q] == op);
+        if (!first)
+            continue;
+        T v = lam.f[fp][op];
+        for (int q = p; q < np; ++q)
+            if (pf[q] == fp && po[q] == op)
+                v = v + (T)(2.0 * rec_row[q]);
+        lam.f[fp][op] = v;
+    }
 }
 
 // mu -= K (Ce lam) on the H nodes the forward H sweep updates.
@@ -142,7 +174,7 @@ template <typename T>
 hipError_t launch_source_probe(const Fields<T> &f, int sf, long long so, double w, int np, const int *pf,
                                const long long *po, double *rec_row, double *J, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_source_probe<T>), dim3(1), dim3(64), 0, s, f, sf, so, w, np, pf, po, rec_row, J);
+    hipLaunchKernelGGL((k_source_probe<T>), dim3(1), dim3(kProbeBlock), 0, s, f, sf, so, w, np, pf, po, rec_row, J);
     return hipGetLastError();
 }
 
@@ -150,7 +182,7 @@ template <typename T>
 hipError_t launch_adj_probe(const Fields<T> &lam, int np, const int *pf, const long long *po, const double *rec_row,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL((k_adj_probe<T>), dim3(1), dim3(64), 0, s, lam, np, pf, po, rec_row);
+    hipLaunchKernelGGL((k_adj_probe<T>), dim3(1), dim3(kProbeBlock), 0, s, lam, np, pf, po, rec_row);
     return hipGetLastError();
 }
 
