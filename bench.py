@@ -79,8 +79,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--n", type=int, default=512, help="cells per axis")
     ap.add_argument("--workload", default="spheres", choices=["spheres", "vacuum"],
-                    help="spheres: 32 seeded inclusions, E seed 3; vacuum: eps_r = 1 passed as an array "
-                         "(uniform per-node Ce arrays still streamed), E seed 2")
+                    help="spheres: 32 seeded inclusions, E seed 3; vacuum: eps_r = mu_r = 1 passed as arrays "
+                         "(uniform per-node Ce and Ch arrays still streamed), E seed 2")
     ap.add_argument("--kernel", default="auto")
     ap.add_argument("--tb-steps", type=int, default=0)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f16c", "bf16c"],
@@ -109,17 +109,19 @@ def main() -> int:
     nx = ny = nz = n
     dx, dt = 1.0, 0.5 / math.sqrt(3.0)
     t0 = time.time()
+    mu = None
     if args.workload == "spheres":
         eps = ci.sphere_eps(nx, ny, nz, seed=33)
         e = ci.random_e(nx, ny, nz, seed=3, dtype=np.float32)
     else:
         eps = np.ones((nz, ny, nx), dtype=np.float64)
+        mu = np.ones((nz, ny, nx), dtype=np.float64)
         e = ci.random_e(nx, ny, nz, seed=2, dtype=np.float32)
     print(f"[bench] inputs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
     torch.cuda.init()
     stream = torch.cuda.Stream()  # default priority; the solver enqueues here and the events time it
-    s = Solver(nx, ny, nz, dx, dt, eps_r=eps, kernel=args.kernel, tb_steps=args.tb_steps, storage=args.storage,
+    s = Solver(nx, ny, nz, dx, dt, eps_r=eps, mu_r=mu, kernel=args.kernel, tb_steps=args.tb_steps, storage=args.storage,
                stream=stream)
     s.set_fields(e)
     tuned = None
@@ -176,7 +178,7 @@ def main() -> int:
 
     result = {
         "metric": f"Gcell-updates/s ({nx}^3 {STORAGE_LABEL[args.storage]} PEC cavity, "
-                  f"{'spherical eps inclusions' if args.workload == 'spheres' else 'vacuum, uniform Ce arrays'})",
+                  f"{'spherical eps inclusions' if args.workload == 'spheres' else 'vacuum, uniform Ce and Ch arrays'})",
         "value": round(gcells, 3),
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
@@ -189,9 +191,9 @@ def main() -> int:
         "dtype": "f32",
         "data": ("synthetic: 32 seeded spherical inclusions eps_r~U[1,4], E~U[-1,1] (SplitMix64), H=0"
                  if args.workload == "spheres" else
-                 "synthetic: vacuum eps_r=1 given as an array, E~U[-1,1] (SplitMix64 seed 2), H=0"),
+                 "synthetic: vacuum eps_r=mu_r=1 given as arrays, E~U[-1,1] (SplitMix64 seed 2), H=0"),
         "config": {"workload": f"box cavity {nx}x{ny}x{nz}, {STORAGE_LABEL[args.storage]} fields, per-node Ce from per-cell eps_r, "
-                               f"scalar Ch, Courant 0.5/sqrt(3)",
+                               f"{'scalar Ch' if mu is None else 'per-node Ch from per-cell mu_r'}, Courant 0.5/sqrt(3)",
                    "kernel": kernel, "steps_per_launch": steps_per_launch, "field_storage": args.storage,
                    "schedule": {k: v for k, v in s_sched.items() if k != "ms_per_step"}, "autotuned": tuned is not None,
                    "parallelism": "single GPU"},

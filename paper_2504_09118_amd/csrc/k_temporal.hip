@@ -259,6 +259,10 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     vec Ecur[TS][3];   // E^{n+s-1}(p_s)
     vec Hold[TS][3];   // H^{n+s-3/2}(p_s)
     vec Hprv[TS][2];   // H^{n+s-1/2}(p_s - 1), x and y
+    // With per-node Ch (one more coefficient pipeline in registers) only the last stage keeps
+    // this copy, as Hlast: for a stage s < TS-1 the same values are Hold[s+1] (same plane and
+    // time level), which the E update reads instead.
+    vec Hlast[2];
     vec Ce[TS][3];     // Ce(p_s)
     vec Ch[TS][3];     // Ch(p_s)
 #pragma unroll
@@ -273,6 +277,8 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
         Hprv[s][0] = zero;
         Hprv[s][1] = zero;
     }
+    Hlast[0] = zero;
+    Hlast[1] = zero;
     vec En1[3] = {zero, zero, zero};  // E^n(p_1 + 1)
 
     const int k0 = max(0, kb - TS);
@@ -370,9 +376,9 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                         const T hy_im = v > 0 ? hout[sp][1][v - 1] : hyl;
                         if (j >= 1 && pp >= 1)
                             ex[v] = curl_update(Ecur[sp][0][v], Ce[sp][0][v], hout[sp][2][v], hzj[v], hout[sp][1][v],
-                                                Hprv[sp][1][v]);
+                                                CH_ARR ? Hold[sp + 1][1][v] : Hprv[sp][1][v]);
                         if (i >= 1 && pp >= 1)
-                            ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], Hprv[sp][0][v],
+                            ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], CH_ARR ? Hold[sp + 1][0][v] : Hprv[sp][0][v],
                                                 hout[sp][2][v], hz_im);
                         if (i >= 1 && j >= 1)
                             ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
@@ -447,9 +453,9 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                     const T hy_im = v > 0 ? hout[sp][1][v - 1] : hyl;
                     if (j >= 1 && pp >= 1)
                         ex[v] = curl_update(Ecur[sp][0][v], Ce[sp][0][v], hout[sp][2][v], hzj[v], hout[sp][1][v],
-                                            Hprv[sp][1][v]);
+                                            CH_ARR ? Hlast[1][v] : Hprv[sp][1][v]);
                     if (i >= 1 && pp >= 1)
-                        ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], Hprv[sp][0][v],
+                        ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], CH_ARR ? Hlast[0][v] : Hprv[sp][0][v],
                                             hout[sp][2][v], hz_im);
                     if (i >= 1 && j >= 1)
                         ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
@@ -474,11 +480,17 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
             eout[sp][1] = ey;
             eout[sp][2] = ez;
         }
+        if (CH_ARR) {
+            Hlast[0] = hout[TS - 1][0];
+            Hlast[1] = hout[TS - 1][1];
+        }
         // ---------------- rotate: stage s feeds stage s+1 at the next plane ----------------
 #pragma unroll
         for (int s = TS - 1; s >= 0; --s) {
-            Hprv[s][0] = hout[s][0];
-            Hprv[s][1] = hout[s][1];
+            if (!CH_ARR) {
+                Hprv[s][0] = hout[s][0];
+                Hprv[s][1] = hout[s][1];
+            }
             if (s + 1 < TS) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
