@@ -196,3 +196,15 @@ def test_backward_leaves_the_start_state():
             g2 = a.backward()
     assert j1 == j2
     assert np.array_equal(g1, g2)
+
+
+def test_duplicate_probes_match_oracle():
+    """A probe listed twice counts twice in J and in the adjoint source (the probe kernels
+    read in parallel and fold duplicates in probe order)."""
+    n, eps, src, probes, wave, e0 = problem24(40)
+    dup = [probes[0], probes[1], probes[0], probes[2], probes[1], probes[0]]
+    J, g, lam0 = gpu_gradient(n, eps, src, dup, wave, e0, "f64", k_every=9)
+    Jr, gr, lr = oracle_gradient(n, eps, src, dup, wave, e0)
+    assert abs(J - Jr) <= 1e-12 * Jr
+    assert rel(g, gr) <= 1e-10
+    assert rel_l2(lam0, lr) <= 1e-10
