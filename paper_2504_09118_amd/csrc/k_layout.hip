@@ -32,6 +32,17 @@ __device__ __forceinline__ bool e_wall(int field, int i, int j, int k, int nx, i
     }
 }
 
+// Wall-normal H node: its update reads only wall-tangential E, so it never changes.
+__device__ __forceinline__ bool h_wall_normal(int field, int i, int j, int k, int nx, int ny, int nz)
+{
+    switch (field) {
+    case 3: return i == 0 || i == nx;
+    case 4: return j == 0 || j == ny;
+    case 5: return k == 0 || k == nz;
+    default: return false;
+    }
+}
+
 template <typename S, typename T>
 __global__ void __launch_bounds__(kBlock) k_pack(Geom g, int field, int X, int Y, long long n,
                                                  const S *__restrict__ src, T *dst, T *dst2, double scale)
@@ -44,6 +55,10 @@ __global__ void __launch_bounds__(kBlock) k_pack(Geom g, int field, int X, int Y
     // scaled in FP64 (exact for scale 1); 16-bit storage: rounded to FP32, then to the 16-bit type
     typename Store<T>::C v = to_compute<T>((double)src[l] * scale);
     if (e_wall(field, i, j, k, g.nx, g.ny, g.nz))
+        v = 0;
+    // a wall-normal H of -0 is stored as +0 (equal values): sweeps that add the zero curl to
+    // every H node then keep every bit
+    if (h_wall_normal(field, i, j, k, g.nx, g.ny, g.nz) && v == 0)
         v = 0;
     long long o = g.at(i, j, k);
     put_elem(dst, g.lo_off, o, v);

@@ -25,6 +25,13 @@
 //     later stages take their inputs from registers of the previous stage;
 //   - a z-chunk starts TS planes early and ends TS-1 planes late so every
 //     stage sees exact inputs on the planes it stores.
+// Walls and the region outside the domain need no per-node predicate: a
+// wall-normal H sees a curl of wall-tangential E (+0, stored as +0, with -0
+// wall-normal H stored as +0), H outside the domain sees only zeros and stays 0,
+// and with per-node Ce arrays (0 on the walls and, as initial value and load
+// result, outside the domain) a wall or outside E gets E + 0 * curl = E. The
+// scalar-Ce E update keeps its wall predicates, and the kernels with per-node
+// Ch keep all of them (the predicate-free form spills registers there).
 // Only the last stage stores, only own cells. Arithmetic per node is
 // curl_update with the operand order of every other schedule: TS sweeps of
 // this kernel equal TS single steps bit for bit.
@@ -200,6 +207,9 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     constexpr int LP = HX + W + HX + V;     // LDS row pitch (one pad vector at the end)
     constexpr int RB = R + 2;               // LDS rows (one pad row each side)
     using vec = typename V2<T>::type;
+    // predicate-free updates (see the file header); the kernels with per-node Ch keep the
+    // predicates: without them their register allocation spills
+    constexpr bool NP_H = !CH_ARR, NP_E = CE_ARR && !CH_ARR;
     __shared__ __attribute__((aligned(16))) T sE[TS][3][RB][LP];  // E input of each stage, plane p_s
     __shared__ __attribute__((aligned(16))) T sH[2][3][RB][LP];   // H of the current stage (alternating)
 
@@ -271,7 +281,9 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
         for (int q = 0; q < 3; ++q) {
             Ecur[s][q] = zero;
             Hold[s][q] = zero;
-            Ce[s][q] = (vec)c.ce_s;
+            // per-node Ce starts at 0 where the E update has no predicates: a lane outside the
+            // domain never loads it, and a zero coefficient makes its E update a no-op
+            Ce[s][q] = NP_E ? zero : (vec)c.ce_s;
             Ch[s][q] = (vec)c.ch_s;
         }
         Hprv[s][0] = zero;
@@ -362,7 +374,7 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                 const bool livep = pp >= lop && pp <= hip;
                 const int hb = (sp + 1) & 1;
                 vec ex = Ecur[sp][0], ey = Ecur[sp][1], ez = Ecur[sp][2];
-                if (livep && act) {
+                if (livep && (NP_E || act)) {
                     const vec hzj = *(const vec *)&sH[hb][2][lr - 1][lc];  // Hz(i, j-1)
                     const vec hxj = *(const vec *)&sH[hb][0][lr - 1][lc];  // Hx(i, j-1)
                     const T hzl = sH[hb][2][lr][lc - 1];                   // Hz(ib-1, j)
@@ -370,17 +382,17 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
                         const int i = ib + v;
-                        if (i >= nx)
+                        if (!NP_E && i >= nx)
                             continue;
                         const T hz_im = v > 0 ? hout[sp][2][v - 1] : hzl;
                         const T hy_im = v > 0 ? hout[sp][1][v - 1] : hyl;
-                        if (j >= 1 && pp >= 1)
+                        if (NP_E || (j >= 1 && pp >= 1))
                             ex[v] = curl_update(Ecur[sp][0][v], Ce[sp][0][v], hout[sp][2][v], hzj[v], hout[sp][1][v],
                                                 CH_ARR ? Hold[sp + 1][1][v] : Hprv[sp][1][v]);
-                        if (i >= 1 && pp >= 1)
+                        if (NP_E || (i >= 1 && pp >= 1))
                             ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], CH_ARR ? Hold[sp + 1][0][v] : Hprv[sp][0][v],
                                                 hout[sp][2][v], hz_im);
-                        if (i >= 1 && j >= 1)
+                        if (NP_E || (i >= 1 && j >= 1))
                             ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
                                                 hxj[v]);
                     }
@@ -398,7 +410,7 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
             const vec *en = s == 0 ? En1 : eout[s - 1];  // E input at plane p+1 (own column)
             const int hb = (s + 1) & 1;
             vec hx = Hold[s][0], hy = Hold[s][1], hz = Hold[s][2];
-            if (live && act) {
+            if (live && (NP_H || act)) {
                 const vec ezj = *(const vec *)&sE[s][2][lr + 1][lc];  // Ez(i, j+1)
                 const vec exj = *(const vec *)&sE[s][0][lr + 1][lc];  // Ex(i, j+1)
                 const T ezr = sE[s][2][lr][lc + V];                    // Ez(ib+V, j)
@@ -406,17 +418,17 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int i = ib + v;
-                    if (i >= nx)
+                    if (!NP_H && i >= nx)
                         continue;
                     const T ez_ip = v + 1 < V ? Ecur[s][2][v + 1] : ezr;
                     const T ey_ip = v + 1 < V ? Ecur[s][1][v + 1] : eyr;
-                    if (i >= 1)
+                    if (NP_H || i >= 1)
                         hx[v] = curl_update(Hold[s][0][v], Ch[s][0][v], en[1][v], Ecur[s][1][v], ezj[v],
                                             Ecur[s][2][v]);
-                    if (j >= 1)
+                    if (NP_H || j >= 1)
                         hy[v] = curl_update(Hold[s][1][v], Ch[s][1][v], ez_ip, Ecur[s][2][v], en[0][v],
                                             Ecur[s][0][v]);
-                    if (p >= 1)
+                    if (NP_H || p >= 1)
                         hz[v] = curl_update(Hold[s][2][v], Ch[s][2][v], exj[v], Ecur[s][0][v], ey_ip,
                                             Ecur[s][1][v]);
                 }
@@ -439,7 +451,7 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
             const bool livep = pp >= lop && pp <= hip;
             const int hb = (sp + 1) & 1;
             vec ex = Ecur[sp][0], ey = Ecur[sp][1], ez = Ecur[sp][2];
-            if (livep && act) {
+            if (livep && (NP_E || act)) {
                 const vec hzj = *(const vec *)&sH[hb][2][lr - 1][lc];
                 const vec hxj = *(const vec *)&sH[hb][0][lr - 1][lc];
                 const T hzl = sH[hb][2][lr][lc - 1];
@@ -447,17 +459,17 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int i = ib + v;
-                    if (i >= nx)
+                    if (!NP_E && i >= nx)
                         continue;
                     const T hz_im = v > 0 ? hout[sp][2][v - 1] : hzl;
                     const T hy_im = v > 0 ? hout[sp][1][v - 1] : hyl;
-                    if (j >= 1 && pp >= 1)
+                    if (NP_E || (j >= 1 && pp >= 1))
                         ex[v] = curl_update(Ecur[sp][0][v], Ce[sp][0][v], hout[sp][2][v], hzj[v], hout[sp][1][v],
                                             CH_ARR ? Hlast[1][v] : Hprv[sp][1][v]);
-                    if (i >= 1 && pp >= 1)
+                    if (NP_E || (i >= 1 && pp >= 1))
                         ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], CH_ARR ? Hlast[0][v] : Hprv[sp][0][v],
                                             hout[sp][2][v], hz_im);
-                    if (i >= 1 && j >= 1)
+                    if (NP_E || (i >= 1 && j >= 1))
                         ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
                                             hxj[v]);
                 }

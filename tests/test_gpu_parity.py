@@ -363,3 +363,34 @@ def test_store_policy_gives_the_same_bits(monkeypatch, kernel, tb):
         outs.append(run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel, tb_steps=tb))
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_wall_normal_h_and_walls_keep_their_bits():
+    """Wall-normal H never changes (a -0 there is stored as +0), wall-tangential E stays +0,
+    and the predicate-free temporal sweeps give the bits of the plain schedule with nonzero
+    wall-normal H constants, with and without per-node Ce."""
+    from paper_2504_09118_amd import field_shapes
+
+    nx, ny, nz, steps = 45, 23, 19, 17
+    e = ci.random_e(nx, ny, nz, seed=51, dtype=np.float32)
+    h = [a.copy() for a in ci.random_h(nx, ny, nz, seed=52, dtype=np.float32)]
+    # (z, y, x) host layout: Hx wall-normal at x = 0, nx; Hy at y = 0, ny; Hz at z = 0, nz
+    h[0][:, :, 0] = -0.0
+    h[0][:, :, nx] = 0.75
+    h[1][:, 0, :] = -0.0
+    h[1][:, ny, :] = -1.25
+    h[2][0, :, :] = 0.5
+    h[2][nz, :, :] = -0.0
+    eps = ci.sphere_eps(nx, ny, nz, seed=53, nspheres=4)
+    for medium in (None, eps):
+        plain = run_gpu(nx, ny, nz, e, h, medium, None, steps, kernel="plain")
+        for tb in (1, 2, 3):
+            got = run_gpu(nx, ny, nz, e, h, medium, None, steps, kernel="temporal", tb_steps=tb)
+            for a, b in zip(got, plain):
+                assert np.array_equal(a, b) and np.array_equal(np.signbit(a), np.signbit(b)), tb
+        hx, hy, hz = plain[3], plain[4], plain[5]
+        assert np.all(hx[:, :, 0] == 0) and not np.any(np.signbit(hx[:, :, 0]))
+        assert np.all(hx[:, :, nx] == 0.75) and np.all(hy[:, ny, :] == -1.25) and np.all(hz[0] == 0.5)
+        assert not np.any(np.signbit(hy[:, 0, :])) and not np.any(np.signbit(hz[nz]))
+        assert oracle.tangential_max(plain) == 0.0
+    assert field_shapes(nx, ny, nz)[3] == h[0].shape
