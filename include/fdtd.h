@@ -159,7 +159,10 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
  * bits): FDTD_ZCHUNKS and FDTD_SLAB_VARIANT (fused / slab z-split and tile
  * shape), FDTD_TZCHUNKS and FDTD_TEMPORAL_VARIANT (temporal sweep),
  * FDTD_NT_STORES = 0 / 1 (store policy; default: non-temporal when one sweep
- * streams more than 256 MB).
+ * streams more than 256 MB), FDTD_XCD_REMAP = 0 / 1 / 2 (workgroup-to-tile
+ * order, read once per process: launch order; one contiguous block of tiles
+ * per XCD; default 2, the temporal sweeps' resident workgroups covering one
+ * contiguous tile range, which the slab sweeps treat as 1).
  */
 int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *coef,
                 const fdtd_opts *opts, fdtd_t *out);

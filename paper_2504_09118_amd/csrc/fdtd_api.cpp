@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -87,8 +88,26 @@ int xcd_remap()
 {
     static const int v = [] {
         const char *e = getenv("FDTD_XCD_REMAP");
-        return (e && *e) ? (atoi(e) != 0) : 1;
+        const int m = (e && *e) ? atoi(e) : 2;
+        return m < 0 ? 0 : (m > 2 ? 2 : m);
     }();
+    return v;
+}
+
+int cus_per_xcd()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        dev = 0;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
+            cus = 256;
+        v = cus / 8;
+        cache[dev].store(v, std::memory_order_relaxed);
+    }
     return v;
 }
 }  // namespace fdtd

@@ -185,9 +185,15 @@ template <typename T>
 hipError_t launch_diag(const Geom &g, const Fields<T> &f, const Coefs<typename Store<T>::C> &c,
                        double *partial, double *out_dev, hipStream_t s);
 
-// Whether the tiled sweeps number their workgroups for the 8 XCDs (1, the
-// default) or in plain launch order (0); FDTD_XCD_REMAP=0 selects the latter.
+// How the tiled sweeps number their workgroups: 0 in plain launch order; 1 so
+// each of the 8 XCDs owns one contiguous block of tiles; 2, the default
+// (temporal sweeps only; the slab sweeps read it as 1), so the workgroups
+// resident at one time, one per CU, cover one contiguous range of tiles, each
+// XCD a contiguous part of it. FDTD_XCD_REMAP selects the mode.
 int xcd_remap();
+
+// Compute units per XCD of the current device (the device's CU count / 8).
+int cus_per_xcd();
 
 // Set the thread-local message fdtd_last_error returns.
 void set_last_error(const char *msg);

@@ -528,20 +528,31 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     }
 }
 
-// XCD-aware tile number of this workgroup: hardware block b runs on XCD b % 8.
-__device__ __forceinline__ int tile_of_block(int ntiles, int xcd_remap)
+// Tile number of this workgroup; hardware block b runs on XCD b % 8.
+// remap 1: XCD x owns tiles [x * nper, (x + 1) * nper).
+// remap 2: one workgroup per CU is resident, so blocks 8 cpx w .. 8 cpx (w + 1) - 1
+// run together; they take the contiguous tile range starting at 8 cpx w, XCD x
+// the x-th part of it, so the halo rows two neighbouring parts share are read
+// at about the same time (the last, partial range is split the same way).
+__device__ __forceinline__ int tile_of_block(int ntiles, int remap, int cpx)
 {
-    const int nper = (ntiles + kXcds - 1) / kXcds;
     const int b = blockIdx.x;
-    return xcd_remap ? (b % kXcds) * nper + b / kXcds : b;
+    if (remap == 0)
+        return b;
+    const int x = b % kXcds, k = b / kXcds;
+    if (remap == 1)
+        return x * ((ntiles + kXcds - 1) / kXcds) + k;
+    const int w = k / cpx, base = w * kXcds * cpx;
+    const int rem = min(kXcds * cpx, ntiles - base);
+    return base + x * ((rem + kXcds - 1) / kXcds) + (k - w * cpx);
 }
 
 template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR, bool NT>
 __global__ void __launch_bounds__(1024)
     k_temporal(Geom g, Fields<S> src, Fields<S> dst, Coefs<typename Store<S>::C> c, int kchunk, int ntx, int nty,
-               int ntiles, int xcd_remap)
+               int ntiles, int remap, int cpx)
 {
-    const int t = tile_of_block(ntiles, xcd_remap);
+    const int t = tile_of_block(ntiles, remap, cpx);
     if (t >= ntiles)
         return;  // the whole workgroup leaves before any barrier
     temporal_tile<S, TS, RPW, CE_ARR, CH_ARR, NT>(g, src, dst, c, kchunk, t % ntx, (t / ntx) % nty, t / (ntx * nty));
@@ -553,9 +564,9 @@ __global__ void __launch_bounds__(1024)
 // a single solve, so each request's bits do not depend on the batch.
 template <int TS, bool CE_ARR, bool CH_ARR>
 __global__ void __launch_bounds__(1024)
-    k_temporal_batch(const BatchEntry *__restrict__ table, int nreq, int ntiles, int xcd_remap)
+    k_temporal_batch(const BatchEntry *__restrict__ table, int nreq, int ntiles, int remap, int cpx)
 {
-    const int t = tile_of_block(ntiles, xcd_remap);
+    const int t = tile_of_block(ntiles, remap, cpx);
     if (t >= ntiles)
         return;
     int lo = 0, hi = nreq - 1;  // last entry with tile_begin <= t
@@ -584,19 +595,20 @@ hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
     const int ntiles = ntx * nty * nzc;
     const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
     dim3 block(64, 16), grid(nblocks);
+    const int rm = xcd_remap(), cpx = cus_per_xcd();
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
     if (cea && cha)
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles, xcd_remap());
+                           ntiles, rm, cpx);
     else if (cea)
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
-                           nty, ntiles, xcd_remap());
+                           nty, ntiles, rm, cpx);
     else if (cha)
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
-                           nty, ntiles, xcd_remap());
+                           nty, ntiles, rm, cpx);
     else
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, false, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx,
-                           nty, ntiles, xcd_remap());
+                           nty, ntiles, rm, cpx);
     return hipGetLastError();
 }
 
@@ -648,9 +660,9 @@ hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, 
         return hipSuccess;
     const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
     dim3 block(64, 16), grid(nblocks);
-    const int rm = xcd_remap();
+    const int rm = xcd_remap(), cpx = cus_per_xcd();
 #define FDTD_BATCH_LAUNCH(TSV, CEV, CHV) \
-    hipLaunchKernelGGL((k_temporal_batch<TSV, CEV, CHV>), grid, block, 0, s, table, nreq, ntiles, rm)
+    hipLaunchKernelGGL((k_temporal_batch<TSV, CEV, CHV>), grid, block, 0, s, table, nreq, ntiles, rm, cpx)
 #define FDTD_BATCH_TS(TSV)                                    \
     do {                                                      \
         if (ce_arr && ch_arr) FDTD_BATCH_LAUNCH(TSV, true, true);   \

@@ -394,3 +394,41 @@ def test_wall_normal_h_and_walls_keep_their_bits():
         assert not np.any(np.signbit(hy[:, 0, :])) and not np.any(np.signbit(hz[nz]))
         assert oracle.tangential_max(plain) == 0.0
     assert field_shapes(nx, ny, nz)[3] == h[0].shape
+
+
+_TILE_ORDER_CHILD = r"""
+import hashlib, sys
+import numpy as np
+import cavity_inputs as ci
+import paper_2504_09118_amd as P
+nx, ny, nz, steps = 300, 301, 64, 7
+eps = ci.sphere_eps(nx, ny, nz, seed=36, nspheres=8)
+e = ci.random_e(nx, ny, nz, seed=15, dtype=np.float32)
+h = ci.random_h(nx, ny, nz, seed=16, dtype=np.float32)
+for kernel, tb in (("temporal", 3), ("temporal", 2), ("slab", 0)):
+    with P.Solver(nx, ny, nz, 1.0, 0.5 / 3 ** 0.5, eps_r=eps, kernel=kernel, tb_steps=tb) as s:
+        s.set_fields(e, h)
+        s.step(steps)
+        d = hashlib.sha256(b"".join(a.tobytes() for a in s.get_fields())).hexdigest()
+    print(kernel, tb, d, flush=True)
+"""
+
+
+def test_tile_order_gives_the_same_bits():
+    """Every workgroup-to-tile order (FDTD_XCD_REMAP, read once per process, so each order
+    runs in a child process) gives the same bits; 7 z-chunks of 5 x 14 tiles make 490
+    temporal tiles, more than one round of resident workgroups and a partial last one."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = []
+    for mode in ("0", "1", "2"):
+        env = dict(os.environ, FDTD_XCD_REMAP=mode, FDTD_TZCHUNKS="7",
+                   PYTHONPATH=os.pathsep.join([root, os.environ.get("PYTHONPATH", "")]))
+        r = subprocess.run([sys.executable, "-c", _TILE_ORDER_CHILD], cwd=root, env=env,
+                           capture_output=True, text=True, timeout=100)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(r.stdout.split())
+    assert len(outs[0]) == 9
+    assert outs[0] == outs[1] == outs[2]
