@@ -162,7 +162,10 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
  * streams more than 256 MB), FDTD_XCD_REMAP = 0 / 1 / 2 (workgroup-to-tile
  * order, read once per process: launch order; one contiguous block of tiles
  * per XCD; default 2, the temporal sweeps' resident workgroups covering one
- * contiguous tile range, which the slab sweeps treat as 1).
+ * contiguous tile range, which the slab sweeps treat as 1),
+ * FDTD_TEMPORAL_SCHED = 0 / 1 (temporal sweeps, read once per process: one
+ * workgroup per tile in the FDTD_XCD_REMAP order; default 1, one workgroup per
+ * CU taking tiles from a queue, except with per-node Ch).
  */
 int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *coef,
                 const fdtd_opts *opts, fdtd_t *out);

@@ -78,6 +78,8 @@ Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool 
         p.staging_bytes = 0;
         p.off_staging = p.off_diag = SIZE_MAX;
     }
+    p.off_sched = off;
+    off += 256;
     p.total = off;
     return p;
 }
@@ -90,6 +92,15 @@ int xcd_remap()
         const char *e = getenv("FDTD_XCD_REMAP");
         const int m = (e && *e) ? atoi(e) : 2;
         return m < 0 ? 0 : (m > 2 ? 2 : m);
+    }();
+    return v;
+}
+
+int temporal_sched()
+{
+    static const int v = [] {
+        const char *e = getenv("FDTD_TEMPORAL_SCHED");
+        return (e && *e) ? (atoi(e) != 0) : 1;
     }();
     return v;
 }
@@ -272,7 +283,7 @@ hipError_t launch_one(fdtd_t h, int kernel, int ts)
         // 16-bit storage is built for the temporal sweep only (ts = 1 for single steps)
         (void)kernel;
         e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                          h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores);
+                                          h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores, h->sched);
     } else {
         if (kernel == FDTD_KERNEL_PLAIN)
             return fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
@@ -281,7 +292,7 @@ hipError_t launch_one(fdtd_t h, int kernel, int ts)
                                           h->zchunk, h->variant, h->stream, h->nt_stores);
         else if (kernel == FDTD_KERNEL_TEMPORAL)
             e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                              h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores);
+                                              h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores, h->sched);
         else
             e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
                                            h->zchunk, h->stream);
@@ -675,6 +686,7 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     }
     h->staging = base + p.off_staging;
     h->diag = (double *)(base + p.off_diag);
+    h->sched = (unsigned *)(base + p.off_sched);
 
     e = hipMemsetAsync(base, 0, p.total, h->stream);
     // materials -> staging -> FP64 coefficient kernel, one material at a time. Rectangular

@@ -81,10 +81,12 @@ hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T>
 // with FP32 coefficients).
 // nt_stores as for the slab step (honoured for FP32 fields; 16-bit fields always
 // store non-temporally).
+// queue: the solver's two scheduling counters (zero before the launch, zero
+// again after it), used when the tiles are handed out from a queue; may be null.
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                                 const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant,
-                                hipStream_t s, bool nt_stores = true);
+                                hipStream_t s, bool nt_stores = true, unsigned *queue = nullptr);
 
 // MI355X's Infinity Cache (256 MB, the last level before HBM). A sweep whose streamed
 // bytes (both state buffers and the coefficient arrays) fit in it keeps the default
@@ -108,9 +110,10 @@ void temporal_tiling(const Geom &g, int ts, int zchunk, int *kchunk, int *ntx, i
 
 // One launch advancing every request of a device table by ts steps; entries
 // sorted by tile_begin, ntiles = total tiles. All entries share ts and the
-// presence of Ce / Ch arrays.
+// presence of Ce / Ch arrays. queue: two scheduling counters as for
+// launch_temporal_step (zero before and after), or null.
 hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, int ts, bool ce_arr, bool ch_arr,
-                                 hipStream_t s);
+                                 hipStream_t s, unsigned *queue = nullptr);
 
 // Device memory plan of one cavity inside an arena (offsets from a 256-byte
 // aligned base): two state buffers of six boxes, optional per-node Ce / Ch
@@ -123,6 +126,7 @@ struct Plan {
     size_t off_ce[3], off_ch[3];
     size_t off_staging, staging_bytes;  // SIZE_MAX / 0 without aux
     size_t off_diag;
+    size_t off_sched;  // 256 bytes of scheduling counters (zero between launches)
     size_t total;
 };
 
@@ -194,6 +198,11 @@ int xcd_remap();
 
 // Compute units per XCD of the current device (the device's CU count / 8).
 int cus_per_xcd();
+
+// How the temporal sweeps hand out tiles: 0 one workgroup per tile, in the
+// FDTD_XCD_REMAP order; 1 (the default; not for the kernels with per-node Ch)
+// one workgroup per CU taking tiles from a queue. FDTD_TEMPORAL_SCHED selects it.
+int temporal_sched();
 
 // Set the thread-local message fdtd_last_error returns.
 void set_last_error(const char *msg);

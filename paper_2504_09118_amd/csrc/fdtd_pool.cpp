@@ -170,6 +170,7 @@ struct fdtd_pool {
     std::unique_ptr<RangeAlloc> alloc;
     BatchEntry *host_tab[kRing];
     BatchEntry *dev_tab[kRing];
+    unsigned *dev_queue;  // tile-queue counters of the batched sweeps (zero between launches)
     hipEvent_t ring_ev[kRing];
     bool ring_busy[kRing];
     int ring_next;
@@ -411,7 +412,7 @@ bool launch_round(fdtd_pool_t p)
         hipError_t e = hipMemcpyAsync(p->dev_tab[slot], tab, (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice,
                                       p->stream);
         if (e == hipSuccess)
-            e = fdtd::launch_temporal_batch(p->dev_tab[slot], n, ntiles, ts, cea, cha, p->stream);
+            e = fdtd::launch_temporal_batch(p->dev_tab[slot], n, ntiles, ts, cea, cha, p->stream, p->dev_queue);
         if (e == hipSuccess)
             e = hipEventRecord(p->ring_ev[slot], p->stream);
         if (e != hipSuccess) {
@@ -529,6 +530,7 @@ void free_pool(fdtd_pool_t p)
         if (p->host_tab[s]) (void)hipHostFree(p->host_tab[s]);
         if (p->dev_tab[s]) (void)hipFree(p->dev_tab[s]);
     }
+    if (p->dev_queue) (void)hipFree(p->dev_queue);
     if (p->own_arena && p->arena) (void)hipFree(p->arena);
     if (p->fetch_stream) (void)hipStreamDestroy(p->fetch_stream);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
@@ -645,6 +647,9 @@ int fdtd_pool_create(const fdtd_pool_opts *opts, fdtd_pool_t *out)
             (e = hipEventCreateWithFlags(&p->ring_ev[s], hipEventDisableTiming)) != hipSuccess)
             return bail(FDTD_E_NOMEM, "request tables", e);
     }
+    if ((e = hipMalloc((void **)&p->dev_queue, 256)) != hipSuccess ||
+        (e = hipMemsetAsync(p->dev_queue, 0, 256, p->stream)) != hipSuccess)
+        return bail(FDTD_E_NOMEM, "tile queue", e);
     {
         std::lock_guard<std::mutex> lk(g_pools_mu);
         g_pools.insert(p);

@@ -25,6 +25,9 @@
 //     later stages take their inputs from registers of the previous stage;
 //   - a z-chunk starts TS planes early and ends TS-1 planes late so every
 //     stage sees exact inputs on the planes it stores.
+//   - by default one workgroup per CU takes tile numbers from a counter in
+//     the solver's arena (the kernels with per-node Ch: one workgroup per
+//     tile, numbered for the XCDs); the tile order never changes the bits.
 // Walls and the region outside the domain need no per-node predicate: a
 // wall-normal H sees a curl of wall-tangential E (+0, stored as +0, with -0
 // wall-normal H stored as +0), H outside the domain sees only zeros and stays 0,
@@ -35,6 +38,7 @@
 // Only the last stage stores, only own cells. Arithmetic per node is
 // curl_update with the operand order of every other schedule: TS sweeps of
 // this kernel equal TS single steps bit for bit.
+#include <algorithm>
 #include <type_traits>
 
 #include "fdtd_internal.h"
@@ -528,18 +532,18 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     }
 }
 
-// Tile number of this workgroup; hardware block b runs on XCD b % 8.
+// Tile number of virtual block v (with one workgroup per tile, v is the
+// hardware block number, and block b runs on XCD b % 8).
 // remap 1: XCD x owns tiles [x * nper, (x + 1) * nper).
 // remap 2: one workgroup per CU is resident, so blocks 8 cpx w .. 8 cpx (w + 1) - 1
 // run together; they take the contiguous tile range starting at 8 cpx w, XCD x
 // the x-th part of it, so the halo rows two neighbouring parts share are read
 // at about the same time (the last, partial range is split the same way).
-__device__ __forceinline__ int tile_of_block(int ntiles, int remap, int cpx)
+__device__ __forceinline__ int tile_of_block(int v, int ntiles, int remap, int cpx)
 {
-    const int b = blockIdx.x;
     if (remap == 0)
-        return b;
-    const int x = b % kXcds, k = b / kXcds;
+        return v;
+    const int x = v % kXcds, k = v / kXcds;
     if (remap == 1)
         return x * ((ntiles + kXcds - 1) / kXcds) + k;
     const int w = k / cpx, base = w * kXcds * cpx;
@@ -547,15 +551,91 @@ __device__ __forceinline__ int tile_of_block(int ntiles, int remap, int cpx)
     return base + x * ((rem + kXcds - 1) / kXcds) + (k - w * cpx);
 }
 
+// Tile queue: one workgroup per CU takes virtual blocks until none is left.
+// Virtual block v (v < nvb, a multiple of 8) sits in list v % 8, in the
+// remap-2 order above; the workgroups on XCD x (hardware register XCC_ID) take
+// list x in order, so the tiles that share halo lines run together in one L2,
+// then help the other lists, so every block is taken exactly once wherever the
+// workgroups run. A CU that ends a tile early starts the next at once, instead
+// of waiting for the dispatcher, which hands out blocks in order round the
+// XCDs and so holds every XCD to the slowest. No workgroup ever waits for
+// another. q[0..7]: next index of each list; q[8]: workgroups done; q[9]: lists
+// seen empty. The one that finishes last has seen every take and zeroes the
+// counters for the next launch (launches sharing them are ordered by their stream).
+constexpr int kQueueWords = kXcds + 2;
+
+struct TileQueue {
+    unsigned *q;
+    int per;   // blocks per list (nvb / 8)
+    int list;  // list taken now
+
+    __device__ explicit TileQueue(unsigned *q_, int nvb) : q(q_), per(nvb / kXcds)
+    {
+        unsigned xcc;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
+        list = (int)(xcc & (kXcds - 1));
+    }
+    // Next virtual block, or -1 when every list is empty (lead lane only). A take
+    // that finds its list empty sets the list's bit in q[9], which then names the
+    // lists every workgroup has seen empty: the workgroup moves to one without a
+    // bit, and leaves when all eight are set. Each list sends a workgroup on at
+    // most once, so the loop ends.
+    __device__ int take()
+    {
+        for (;;) {
+            const int j = (int)atomicAdd(&q[list], 1u);
+            if (j < per)
+                return j * kXcds + list;
+            const unsigned empty = atomicOr(&q[kXcds + 1], 1u << list) | (1u << list);
+            if (empty == 0xffu)
+                return -1;
+            list = __ffs(~empty) - 1;
+        }
+    }
+    __device__ void finish()
+    {
+        if (atomicAdd(&q[kXcds], 1u) == gridDim.x - 1)
+            for (int i = 0; i < kQueueWords; ++i)
+                atomicExch(&q[i], 0u);
+    }
+};
+
 template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR, bool NT>
 __global__ void __launch_bounds__(1024)
     k_temporal(Geom g, Fields<S> src, Fields<S> dst, Coefs<typename Store<S>::C> c, int kchunk, int ntx, int nty,
                int ntiles, int remap, int cpx)
 {
-    const int t = tile_of_block(ntiles, remap, cpx);
+    const int t = tile_of_block(blockIdx.x, ntiles, remap, cpx);
     if (t >= ntiles)
         return;  // the whole workgroup leaves before any barrier
     temporal_tile<S, TS, RPW, CE_ARR, CH_ARR, NT>(g, src, dst, c, kchunk, t % ntx, (t / ntx) % nty, t / (ntx * nty));
+}
+
+// Queue schedule (TileQueue above).
+template <typename S, int TS, int RPW, bool CE_ARR, bool CH_ARR, bool NT>
+__global__ void __launch_bounds__(1024)
+    k_temporal_q(Geom g, Fields<S> src, Fields<S> dst, Coefs<typename Store<S>::C> c, int kchunk, int ntx, int nty,
+                 int ntiles, int nvb, int cpx, unsigned *queue)
+{
+    __shared__ int s_v;
+    const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+    TileQueue tq(queue, nvb);
+    for (;;) {
+        if (lead)
+            s_v = tq.take();
+        __syncthreads();
+        const int v = s_v;
+        __syncthreads();  // every lane has read s_v before the next take rewrites it
+        if (v < 0)
+            break;  // the same for the whole workgroup
+        const int t = tile_of_block(v, ntiles, 2, cpx);
+        if (t < ntiles)
+            temporal_tile<S, TS, RPW, CE_ARR, CH_ARR, NT>(g, src, dst, c, kchunk, t % ntx, (t / ntx) % nty,
+                                                          t / (ntx * nty));
+        __syncthreads();  // the next tile rewrites the LDS this one read last
+    }
+    if (lead)
+        tq.finish();
 }
 
 // One launch over the tiles of several cavities (continuous batching): the
@@ -563,12 +643,8 @@ __global__ void __launch_bounds__(1024)
 // request's own geometry, buffers and coefficients run the same tile code as
 // a single solve, so each request's bits do not depend on the batch.
 template <int TS, bool CE_ARR, bool CH_ARR>
-__global__ void __launch_bounds__(1024)
-    k_temporal_batch(const BatchEntry *__restrict__ table, int nreq, int ntiles, int remap, int cpx)
+__device__ __forceinline__ void batch_tile(const BatchEntry *__restrict__ table, int nreq, int t)
 {
-    const int t = tile_of_block(ntiles, remap, cpx);
-    if (t >= ntiles)
-        return;
     int lo = 0, hi = nreq - 1;  // last entry with tile_begin <= t
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -583,9 +659,44 @@ __global__ void __launch_bounds__(1024)
                                                 u / (e.ntx * e.nty));
 }
 
+template <int TS, bool CE_ARR, bool CH_ARR>
+__global__ void __launch_bounds__(1024)
+    k_temporal_batch(const BatchEntry *__restrict__ table, int nreq, int ntiles, int remap, int cpx)
+{
+    const int t = tile_of_block(blockIdx.x, ntiles, remap, cpx);
+    if (t >= ntiles)
+        return;
+    batch_tile<TS, CE_ARR, CH_ARR>(table, nreq, t);
+}
+
+// The batched launch with the tile queue of k_temporal_q (the pool's own counters).
+template <int TS, bool CE_ARR>
+__global__ void __launch_bounds__(1024)
+    k_temporal_batch_q(const BatchEntry *__restrict__ table, int nreq, int ntiles, int nvb, int cpx, unsigned *queue)
+{
+    __shared__ int s_v;
+    const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+    TileQueue tq(queue, nvb);
+    for (;;) {
+        if (lead)
+            s_v = tq.take();
+        __syncthreads();
+        const int v = s_v;
+        __syncthreads();
+        if (v < 0)
+            break;
+        const int t = tile_of_block(v, ntiles, 2, cpx);
+        if (t < ntiles)
+            batch_tile<TS, CE_ARR, false>(table, nreq, t);
+        __syncthreads();
+    }
+    if (lead)
+        tq.finish();
+}
+
 template <typename T, int TS, int RPW, bool NT>
 hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
-                     const Coefs<typename Store<T>::C> &c, int zchunk, hipStream_t s)
+                     const Coefs<typename Store<T>::C> &c, int zchunk, hipStream_t s, unsigned *queue)
 {
     using Sh = TShape<TS, RPW>;
     const int kchunk = (g.nz + zchunk - 1) / zchunk;
@@ -593,10 +704,25 @@ hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
     const int own = Sh::R - 2 * TS;
     const int ntx = (g.nx + Sh::W - 1) / Sh::W, nty = (g.ny + own - 1) / own;
     const int ntiles = ntx * nty * nzc;
-    const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
-    dim3 block(64, 16), grid(nblocks);
-    const int rm = xcd_remap(), cpx = cus_per_xcd();
+    const int cpx = cus_per_xcd();
+    dim3 block(64, 16);
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
+    // the queue form of the kernels with per-node Ch spills registers: they keep one
+    // workgroup per tile
+    if (queue && !cha && temporal_sched() == 1) {
+        const int nvb = (ntiles + kXcds - 1) / kXcds * kXcds;
+        dim3 grid(std::min(ntiles, kXcds * cpx));  // one workgroup per CU
+        if (cea)
+            hipLaunchKernelGGL((k_temporal_q<T, TS, RPW, true, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk,
+                               ntx, nty, ntiles, nvb, cpx, queue);
+        else
+            hipLaunchKernelGGL((k_temporal_q<T, TS, RPW, false, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk,
+                               ntx, nty, ntiles, nvb, cpx, queue);
+        return hipGetLastError();
+    }
+    const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
+    dim3 grid(nblocks);
+    const int rm = xcd_remap();
     if (cea && cha)
         hipLaunchKernelGGL((k_temporal<T, TS, RPW, true, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
                            ntiles, rm, cpx);
@@ -614,20 +740,21 @@ hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
 
 template <typename T, bool NT>
 hipError_t launch_shape(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
-                        const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant, hipStream_t s)
+                        const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant, hipStream_t s,
+                        unsigned *queue)
 {
     if (variant == 1) {
         switch (ts) {
-        case 1: return launch_ts<T, 1, 1, NT>(g, src, dst, c, zchunk, s);
-        case 2: return launch_ts<T, 2, 1, NT>(g, src, dst, c, zchunk, s);
-        case 3: return launch_ts<T, 3, 1, NT>(g, src, dst, c, zchunk, s);
+        case 1: return launch_ts<T, 1, 1, NT>(g, src, dst, c, zchunk, s, queue);
+        case 2: return launch_ts<T, 2, 1, NT>(g, src, dst, c, zchunk, s, queue);
+        case 3: return launch_ts<T, 3, 1, NT>(g, src, dst, c, zchunk, s, queue);
         default: return hipErrorInvalidValue;
         }
     }
     switch (ts) {
-    case 1: return launch_ts<T, 1, 2, NT>(g, src, dst, c, zchunk, s);
-    case 2: return launch_ts<T, 2, 2, NT>(g, src, dst, c, zchunk, s);
-    case 3: return launch_ts<T, 3, 2, NT>(g, src, dst, c, zchunk, s);
+    case 1: return launch_ts<T, 1, 2, NT>(g, src, dst, c, zchunk, s, queue);
+    case 2: return launch_ts<T, 2, 2, NT>(g, src, dst, c, zchunk, s, queue);
+    case 3: return launch_ts<T, 3, 2, NT>(g, src, dst, c, zchunk, s, queue);
     default: return hipErrorInvalidValue;
     }
 }
@@ -654,10 +781,29 @@ void temporal_tiling(const Geom &g, int ts, int zchunk, int *kchunk, int *ntx, i
 }
 
 hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, int ts, bool ce_arr, bool ch_arr,
-                                 hipStream_t s)
+                                 hipStream_t s, unsigned *queue)
 {
     if (nreq <= 0 || ntiles <= 0)
         return hipSuccess;
+    if (queue && !ch_arr && temporal_sched() == 1) {
+        const int cpx = cus_per_xcd(), nvb = (ntiles + kXcds - 1) / kXcds * kXcds;
+        dim3 block(64, 16), grid(std::min(ntiles, kXcds * cpx));
+#define FDTD_BATCH_Q(TSV)                                                                                          \
+    do {                                                                                                           \
+        if (ce_arr)                                                                                                \
+            hipLaunchKernelGGL((k_temporal_batch_q<TSV, true>), grid, block, 0, s, table, nreq, ntiles, nvb, cpx, queue);  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_temporal_batch_q<TSV, false>), grid, block, 0, s, table, nreq, ntiles, nvb, cpx, queue); \
+    } while (0)
+        switch (ts) {
+        case 1: FDTD_BATCH_Q(1); break;
+        case 2: FDTD_BATCH_Q(2); break;
+        case 3: FDTD_BATCH_Q(3); break;
+        default: return hipErrorInvalidValue;
+        }
+#undef FDTD_BATCH_Q
+        return hipGetLastError();
+    }
     const int nblocks = (ntiles + kXcds - 1) / kXcds * kXcds;
     dim3 block(64, 16), grid(nblocks);
     const int rm = xcd_remap(), cpx = cus_per_xcd();
@@ -684,28 +830,28 @@ hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, 
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                                 const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant,
-                                hipStream_t s, bool nt_stores)
+                                hipStream_t s, bool nt_stores, unsigned *queue)
 {
     zchunk = zchunk < 1 ? 1 : zchunk;
     // the default-policy stores are built for FP32 fields only (the small, cache-resident
     // states that profit from them are FP32 in practice)
     if constexpr (std::is_same<T, float>::value)
         if (!nt_stores)
-            return launch_shape<T, false>(g, src, dst, c, zchunk, ts, variant, s);
+            return launch_shape<T, false>(g, src, dst, c, zchunk, ts, variant, s, queue);
     (void)nt_stores;
-    return launch_shape<T, true>(g, src, dst, c, zchunk, ts, variant, s);
+    return launch_shape<T, true>(g, src, dst, c, zchunk, ts, variant, s, queue);
 }
 
 template hipError_t launch_temporal_step<float>(const Geom &, const Fields<float> &, const Fields<float> &,
-                                                const Coefs<float> &, int, int, int, hipStream_t, bool);
+                                                const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
 template hipError_t launch_temporal_step<f16>(const Geom &, const Fields<f16> &, const Fields<f16> &,
-                                              const Coefs<float> &, int, int, int, hipStream_t, bool);
+                                              const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
 template hipError_t launch_temporal_step<bf16>(const Geom &, const Fields<bf16> &, const Fields<bf16> &,
-                                               const Coefs<float> &, int, int, int, hipStream_t, bool);
+                                               const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
 template hipError_t launch_temporal_step<f16c>(const Geom &, const Fields<f16c> &, const Fields<f16c> &,
-                                               const Coefs<float> &, int, int, int, hipStream_t, bool);
+                                               const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
 template hipError_t launch_temporal_step<bf16c>(const Geom &, const Fields<bf16c> &, const Fields<bf16c> &,
-                                                const Coefs<float> &, int, int, int, hipStream_t, bool);
+                                                const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
 
 }  // namespace fdtd
 
@@ -714,7 +860,7 @@ namespace fdtd {
 // FP64 storage has no temporal kernel (its LDS tiles would not fit); create rejects it.
 template <>
 hipError_t launch_temporal_step<double>(const Geom &, const Fields<double> &, const Fields<double> &,
-                                        const Coefs<double> &, int, int, int, hipStream_t, bool)
+                                        const Coefs<double> &, int, int, int, hipStream_t, bool, unsigned *)
 {
     return hipErrorNotSupported;
 }

@@ -31,6 +31,7 @@ struct fdtd_solver {
     double ce_s, ch_s;
     void *staging;
     double *diag;
+    unsigned *sched;  // scheduling counters of the temporal sweep (arena)
     int cur;
     long long steps, sweeps;
     bool failed, fields_set;

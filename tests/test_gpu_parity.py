@@ -415,20 +415,22 @@ for kernel, tb in (("temporal", 3), ("temporal", 2), ("slab", 0)):
 
 
 def test_tile_order_gives_the_same_bits():
-    """Every workgroup-to-tile order (FDTD_XCD_REMAP, read once per process, so each order
-    runs in a child process) gives the same bits; 7 z-chunks of 5 x 14 tiles make 490
-    temporal tiles, more than one round of resident workgroups and a partial last one."""
+    """Every workgroup-to-tile order (FDTD_XCD_REMAP) and the queue schedule of the temporal
+    sweeps (FDTD_TEMPORAL_SCHED; both read once per process, so each setting runs in a child
+    process) give the same bits; 7 z-chunks of 5 x 14 tiles make 490 temporal tiles, more
+    than one round of resident workgroups and a partial last one, and the 7 steps make two
+    queue launches in a row (the queue counters must be back at zero for the second)."""
     import subprocess
     import sys
 
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     outs = []
-    for mode in ("0", "1", "2"):
-        env = dict(os.environ, FDTD_XCD_REMAP=mode, FDTD_TZCHUNKS="7",
+    for sched, mode in (("0", "0"), ("0", "1"), ("0", "2"), ("1", "2")):
+        env = dict(os.environ, FDTD_XCD_REMAP=mode, FDTD_TEMPORAL_SCHED=sched, FDTD_TZCHUNKS="7",
                    PYTHONPATH=os.pathsep.join([root, os.environ.get("PYTHONPATH", "")]))
         r = subprocess.run([sys.executable, "-c", _TILE_ORDER_CHILD], cwd=root, env=env,
                            capture_output=True, text=True, timeout=100)
         assert r.returncode == 0, r.stderr[-2000:]
         outs.append(r.stdout.split())
     assert len(outs[0]) == 9
-    assert outs[0] == outs[1] == outs[2]
+    assert all(o == outs[0] for o in outs[1:])
