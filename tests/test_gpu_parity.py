@@ -434,3 +434,57 @@ def test_tile_order_gives_the_same_bits():
         outs.append(r.stdout.split())
     assert len(outs[0]) == 9
     assert all(o == outs[0] for o in outs[1:])
+
+
+def test_two_solvers_on_two_streams_keep_their_bits():
+    """Two solvers stepping at once on their own streams, each with its own tile-queue
+    counters in its arena, give the bits each gives alone; the calls interleave, so the two
+    solvers' temporal sweeps can run on the device at the same time."""
+    import torch
+
+    dims = [(150, 90, 60), (97, 130, 41)]
+    ins = []
+    for q, (nx, ny, nz) in enumerate(dims):
+        eps = ci.sphere_eps(nx, ny, nz, seed=60 + q, nspheres=5)
+        e = ci.random_e(nx, ny, nz, seed=62 + q, dtype=np.float32)
+        h = ci.random_h(nx, ny, nz, seed=64 + q, dtype=np.float32)
+        ins.append((eps, e, h))
+    alone = [run_gpu(*d, e, h, eps, None, 12, kernel="temporal", tb_steps=3) for d, (eps, e, h) in zip(dims, ins)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    solvers = [_solver(*d, 1.0, S, eps_r=eps, kernel="temporal", tb_steps=3, stream=st)
+               for d, (eps, _, _), st in zip(dims, ins, streams)]
+    try:
+        for s, (_, e, h) in zip(solvers, ins):
+            s.set_fields(e, h)
+        for _ in range(4):
+            for s in solvers:
+                s.step(3)
+        got = [s.get_fields() for s in solvers]
+    finally:
+        for s in solvers:
+            s.close()
+    for g, a in zip(got, alone):
+        for x, y in zip(g, a):
+            assert np.array_equal(x, y)
+
+
+def test_schedule_changes_between_sweeps_keep_the_bits():
+    """Launches with different tile counts follow each other on one solver's queue counters
+    (TS = 3, 2, 1 and 3 again, then two z-splits): the counters are back at zero after each
+    launch, so the state equals the plain schedule's bit for bit."""
+    nx, ny, nz = 130, 70, 50
+    eps = ci.sphere_eps(nx, ny, nz, seed=66, nspheres=5)
+    e = ci.random_e(nx, ny, nz, seed=67, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=68, dtype=np.float32)
+    plain = run_gpu(nx, ny, nz, e, h, eps, None, 21, kernel="plain")
+    with _solver(nx, ny, nz, 1.0, S, eps_r=eps, kernel="temporal", tb_steps=3) as s:
+        s.set_fields(e, h)
+        for tb, zc, n in ((3, 0, 6), (2, 0, 4), (1, 0, 2), (3, 5, 3), (3, 1, 6)):
+            if zc:
+                s.set_schedule("temporal", tb_steps=tb, zchunks=zc)
+            else:
+                s.set_schedule("temporal", tb_steps=tb, zchunks=s.schedule["zchunks"])
+            s.step(n)
+        got = s.get_fields()
+    for x, y in zip(got, plain):
+        assert np.array_equal(x, y)
