@@ -199,7 +199,11 @@ int fdtd_init_random(fdtd_t h, unsigned long long seed);
  * Enqueue n >= 0 leapfrog steps (Sec. 2.1 algorithm listing: H update, H
  * boundary, E update, E boundary). Asynchronous: returns after launching.
  * Launch failures return FDTD_E_DEVICE at once; faults during execution
- * surface at the next fdtd_sync / fdtd_get_fields.
+ * surface at the next fdtd_sync / fdtd_get_fields. The temporal sweeps hand
+ * out tiles from counters in the solver's arena, which every launch leaves at
+ * zero: launches on one solver must stay ordered on its stream (as they are
+ * when issued through this call, also inside a captured graph that is
+ * replayed on one stream); different solvers share nothing.
  */
 int fdtd_step(fdtd_t h, long long n);
 
