@@ -302,12 +302,15 @@ int fdtd_destroy(fdtd_t h);
  * fdtd_adjoint_backward returns dJ/d eps_r per cell by the discrete adjoint:
  * the same curl stencils run in reverse time with the coefficient inside the
  * curl (the E curl is minus the transpose of the H curl), accumulating
- * dJ/dCe = sum_n lam^{n+1} (L H^{n+1/2}) per edge in FP64, then
+ * dJ/dCe = sum_n lam^{n+1} (L H^{n+1/2}) per edge in FP64 (with FP32
+ * storage the terms are first summed in FP32 over fixed groups of 16 steps,
+ * n = 16m .. 16m+15, independent of the checkpoint interval), then
  * dJ/d eps_cell = sum over the cell's 12 edges of dJ/dCe * (-Ce^2 dx/dt / 4)
  * (Ce = dt/(dx * mean eps of the edge's four cells)). The forward pass stores
  * (E^n, H^{n-1/2}) every checkpoint_every steps; the backward pass recomputes
  * each segment from its checkpoint (checkpoint-and-recompute), so device
- * memory is ceil(N/K) states + K H-fields, not N.
+ * memory is ceil(N/K) states + K H-fields (+ the FP64 gradient boxes and,
+ * with FP32 storage, their FP32 group sums), not N.
  */
 typedef struct fdtd_adjoint *fdtd_adjoint_t;
 

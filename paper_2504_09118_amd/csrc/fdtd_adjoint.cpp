@@ -80,6 +80,7 @@ struct fdtd_adjoint {
     char *ckpt, *hist;
     void *adj[6];  // lam Ex Ey Ez, mu Hx Hy Hz (element (0,0,0) of each box)
     double *gce[3];
+    float *gpart[3];  // FP32 group sums of the gCe terms (FP32 storage), else null
     bool forward_done;
 };
 
@@ -185,6 +186,9 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
     for (int q = 0; q < 3 && e == hipSuccess; ++q)
         e = hipMemsetAsync((char *)a->gce[q] - fdtd::kGuardElems * sizeof(double), 0,
                            (size_t)g.box * sizeof(double), s->stream);
+    for (int q = 0; q < 3 && a->gpart[0] && e == hipSuccess; ++q)
+        e = hipMemsetAsync((char *)a->gpart[q] - fdtd::kGuardElems * sizeof(float), 0,
+                           (size_t)g.box * sizeof(float), s->stream);
     if (e == hipSuccess)
         e = fdtd::launch_adj_probe<T>(adj, a->np, a->d_pf, a->d_po, a->d_rec + (size_t)a->N * a->np, s->stream);
     if (e != hipSuccess)
@@ -225,7 +229,9 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
         for (long long n = n1 - 1; n >= n0; --n) {
             const T *h[3];
             for (int f = 0; f < 3; ++f) h[f] = slot_h(n - n0, f);
-            e = fdtd::launch_adj_step<T>(g, adj, c, h, a->gce, s->stream);
+            // the step n with n % kAdjGroup == 0 closes its group (n = 0 closes the last)
+            e = fdtd::launch_adj_step<T>(g, adj, c, h, a->gce, a->gpart[0] ? a->gpart : nullptr,
+                                         n % fdtd::kAdjGroup == 0, s->stream);
             if (e == hipSuccess && n >= 1)
                 e = fdtd::launch_adj_probe<T>(adj, a->np, a->d_pf, a->d_po, a->d_rec + (size_t)n * a->np,
                                               s->stream);
@@ -337,6 +343,12 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
     off += 6 * a->fbox;
     const size_t o_gce = off;
     off += 3 * gbox;
+    // FP32 storage: the per-step gCe terms are summed in FP32 over groups of kAdjGroup steps
+    const bool grouped = s->storage == FDTD_F32;
+    const size_t pbox = ((size_t)g.box * sizeof(float) + 255) / 256 * 256;
+    const size_t o_gpart = off;
+    if (grouped)
+        off += 3 * pbox;
     const size_t o_grad = off;
     off += up(ncell * sizeof(double));
     const size_t o_rec = off;
@@ -358,6 +370,8 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
     for (int q = 0; q < 6; ++q) a->adj[q] = a->mem + o_adj + (size_t)q * a->fbox + a->guard;
     for (int q = 0; q < 3; ++q)
         a->gce[q] = (double *)(a->mem + o_gce + (size_t)q * gbox) + fdtd::kGuardElems;
+    for (int q = 0; q < 3; ++q)
+        a->gpart[q] = grouped ? (float *)(a->mem + o_gpart + (size_t)q * pbox) + fdtd::kGuardElems : nullptr;
     a->d_grad = (double *)(a->mem + o_grad);
     a->d_rec = (double *)(a->mem + o_rec);
     a->d_J = (double *)(a->mem + o_j);

@@ -151,9 +151,12 @@ template <typename T>
 hipError_t launch_adj_probe(const Fields<T> &lam, int np, const int *pf, const long long *po, const double *rec_row,
                             hipStream_t s);
 // One reverse step: a = (lam Ex Ey Ez, mu Hx Hy Hz); hist = H^{n+1/2}; gce += lam (L hist).
+// gpart (null: gce directly): FP32 group sums (boxes like gce, zero at a group's start)
+// that collect the term; close_group adds them to gce and clears them.
+constexpr int kAdjGroup = 16;
 template <typename T>
 hipError_t launch_adj_step(const Geom &g, const Fields<T> &a, const Coefs<T> &c, const T *const hist[3],
-                           double *const gce[3], hipStream_t s);
+                           double *const gce[3], float *const gpart[3], bool close_group, hipStream_t s);
 // dJ/d eps per cell (dense x-fastest nx*ny*nz doubles) from dJ/dCe per edge.
 template <typename T>
 hipError_t launch_grad_eps(const Geom &g, const Coefs<T> &c, double *const gce[3], double dx_over_dt, double *out,

@@ -14,7 +14,12 @@
 // L = -K^T on the updated nodes, which turns the transposes into the same
 // stencils with the coefficient inside the curl and a minus sign. Nodes the
 // forward never updates (wall-tangential E, wall-normal H) keep lam = mu = 0.
-// The gradient accumulates in FP64; the stencils run in the storage type.
+// The gradient accumulates in FP64; the stencils run in the storage type. With
+// FP32 storage each step's gCe term is first summed in FP32 over fixed groups
+// of kAdjGroup reverse steps (the steps n with n % kAdjGroup == 0 close a
+// group, whatever the checkpoint interval, so the bits do not depend on it)
+// and each group's sum is added to the FP64 total: the FP64 array is read and
+// written once per group instead of every step.
 #include "fdtd_internal.h"
 #include "yee_update.h"
 
@@ -107,10 +112,30 @@ __global__ void __launch_bounds__(kBX *kBY) k_adj_mu(Geom g, Fields<T> a, Coefs<
 }
 
 // gCe += lam (L H^{n+1/2}); lam -= L (Ch mu), on the interior E nodes.
-template <typename T, bool CH_ARR>
+// GM 0: gCe in g (FP64) directly; 1: into the FP32 group sums p; 2: into p, then
+// p is added to g and cleared (the last step of a group).
+template <int GM, typename T>
+__device__ __forceinline__ void add_gce(double *g, float *p, long long o, T l, T lh)
+{
+    if constexpr (GM == 0) {
+        (void)p;
+        g[o] += (double)l * (double)lh;
+    } else {
+        const float v = p[o] + (float)l * (float)lh;
+        if constexpr (GM == 2) {
+            g[o] += (double)v;
+            p[o] = 0.0f;
+        } else {
+            (void)g;
+            p[o] = v;
+        }
+    }
+}
+
+template <typename T, bool CH_ARR, int GM>
 __global__ void __launch_bounds__(kBX *kBY)
     k_adj_lam(Geom g, Fields<T> a, Coefs<T> c, const T *__restrict__ hx, const T *__restrict__ hy,
-              const T *__restrict__ hz, double *gx, double *gy, double *gz)
+              const T *__restrict__ hz, double *gx, double *gy, double *gz, float *px, float *py, float *pz)
 {
     const int i = blockIdx.x * kBX + threadIdx.x;
     const int j = blockIdx.y * kBY + threadIdx.y;
@@ -118,28 +143,28 @@ __global__ void __launch_bounds__(kBX *kBY)
     if (i >= g.nx || j >= g.ny)
         return;
     const long long o = g.at(i, j, k), P = g.plane;
-    const int px = g.px;
+    const int px_ = g.px;
     T *lx = a.f[0], *ly = a.f[1], *lz = a.f[2];
     const T *mx = a.f[3], *my = a.f[4], *mz = a.f[5];
     auto b = [&](int q, const T *m, long long idx) -> T { return (CH_ARR ? c.ch[q][idx] : c.ch_s) * m[idx]; };
     const T m1 = (T)-1;
     if (j >= 1 && k >= 1) {
         const T l = lx[o];
-        const T lh = (hz[o] - hz[o - px]) - (hy[o] - hy[o - P]);
-        gx[o] += (double)l * (double)lh;
-        lx[o] = curl_update(l, m1, b(2, mz, o), b(2, mz, o - px), b(1, my, o), b(1, my, o - P));
+        const T lh = (hz[o] - hz[o - px_]) - (hy[o] - hy[o - P]);
+        add_gce<GM>(gx, px, o, l, lh);
+        lx[o] = curl_update(l, m1, b(2, mz, o), b(2, mz, o - px_), b(1, my, o), b(1, my, o - P));
     }
     if (i >= 1 && k >= 1) {
         const T l = ly[o];
         const T lh = (hx[o] - hx[o - P]) - (hz[o] - hz[o - 1]);
-        gy[o] += (double)l * (double)lh;
+        add_gce<GM>(gy, py, o, l, lh);
         ly[o] = curl_update(l, m1, b(0, mx, o), b(0, mx, o - P), b(2, mz, o), b(2, mz, o - 1));
     }
     if (i >= 1 && j >= 1) {
         const T l = lz[o];
-        const T lh = (hy[o] - hy[o - 1]) - (hx[o] - hx[o - px]);
-        gz[o] += (double)l * (double)lh;
-        lz[o] = curl_update(l, m1, b(1, my, o), b(1, my, o - 1), b(0, mx, o), b(0, mx, o - px));
+        const T lh = (hy[o] - hy[o - 1]) - (hx[o] - hx[o - px_]);
+        add_gce<GM>(gz, pz, o, l, lh);
+        lz[o] = curl_update(l, m1, b(1, my, o), b(1, my, o - 1), b(0, mx, o), b(0, mx, o - px_));
     }
 }
 
@@ -188,16 +213,27 @@ hipError_t launch_adj_probe(const Fields<T> &lam, int np, const int *pf, const l
 
 template <typename T>
 hipError_t launch_adj_step(const Geom &g, const Fields<T> &a, const Coefs<T> &c, const T *const hist[3],
-                           double *const gce[3], hipStream_t s)
+                           double *const gce[3], float *const gpart[3], bool close_group, hipStream_t s)
 {
     dim3 block(kBX, kBY), grid((g.nx + kBX - 1) / kBX, (g.ny + kBY - 1) / kBY, g.nz);
     hipLaunchKernelGGL((k_adj_mu<T>), grid, block, 0, s, g, a, c);
-    if (c.ch[0])
-        hipLaunchKernelGGL((k_adj_lam<T, true>), grid, block, 0, s, g, a, c, hist[0], hist[1], hist[2], gce[0],
-                           gce[1], gce[2]);
-    else
-        hipLaunchKernelGGL((k_adj_lam<T, false>), grid, block, 0, s, g, a, c, hist[0], hist[1], hist[2], gce[0],
-                           gce[1], gce[2]);
+    float *p0 = gpart ? gpart[0] : nullptr, *p1 = gpart ? gpart[1] : nullptr, *p2 = gpart ? gpart[2] : nullptr;
+#define FDTD_ADJ_LAM(CHV, GMV)                                                                                   \
+    hipLaunchKernelGGL((k_adj_lam<T, CHV, GMV>), grid, block, 0, s, g, a, c, hist[0], hist[1], hist[2], gce[0], \
+                       gce[1], gce[2], p0, p1, p2)
+    const int gm = !gpart ? 0 : (close_group ? 2 : 1);
+    const bool cha = c.ch[0] != nullptr;
+    if (gm == 0) {
+        if (cha) FDTD_ADJ_LAM(true, 0);
+        else FDTD_ADJ_LAM(false, 0);
+    } else if (gm == 1) {
+        if (cha) FDTD_ADJ_LAM(true, 1);
+        else FDTD_ADJ_LAM(false, 1);
+    } else {
+        if (cha) FDTD_ADJ_LAM(true, 2);
+        else FDTD_ADJ_LAM(false, 2);
+    }
+#undef FDTD_ADJ_LAM
     return hipGetLastError();
 }
 
@@ -217,7 +253,7 @@ hipError_t launch_grad_eps(const Geom &g, const Coefs<T> &c, double *const gce[3
     template hipError_t launch_adj_probe<T>(const Fields<T> &, int, const int *, const long long *,           \
                                             const double *, hipStream_t);                                      \
     template hipError_t launch_adj_step<T>(const Geom &, const Fields<T> &, const Coefs<T> &, const T *const[3], \
-                                           double *const[3], hipStream_t);                                     \
+                                           double *const[3], float *const[3], bool, hipStream_t);              \
     template hipError_t launch_grad_eps<T>(const Geom &, const Coefs<T> &, double *const[3], double, double *, \
                                            hipStream_t);
 FDTD_ADJ_INST(float)
