@@ -237,3 +237,36 @@ def test_create_rejects_oversized_planes():
     st, h = _create(24000, 24000, 2)
     assert st == F.E_ARG and not h.value
     assert b"plane" in F.load_library().fdtd_last_error()
+
+
+def test_recorded_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
+    """bench.py reports counter-measured traffic only while the kernel source still has the
+    sha256 recorded with it: the committed record matches the committed source, and a record
+    whose source differs (here: a copy of the tree with one byte changed) reads as unknown."""
+    import hashlib
+    import shutil
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    try:
+        import bench
+    finally:
+        sys.path.remove(root)
+    traffic, summary = bench.recorded_traffic("temporal", 3, 512)
+    assert traffic is not None and summary.startswith("profiles/")
+    rec = [ln.split() for ln in open(os.path.join(root, "profiles", "traffic_records.txt"))
+           if ln.strip() and not ln.startswith("#")]
+    for k, tb, n, src, sha, rd, wr, summ in rec:
+        with open(os.path.join(root, src), "rb") as f:
+            assert hashlib.sha256(f.read()).hexdigest() == sha, src
+        assert os.path.exists(os.path.join(root, summ))
+    # a tree whose kernel source differs from the recorded one
+    (tmp_path / "profiles").mkdir()
+    shutil.copy(os.path.join(root, "profiles", "traffic_records.txt"), tmp_path / "profiles")
+    src = rec[0][3]
+    (tmp_path / src).parent.mkdir(parents=True)
+    data = open(os.path.join(root, src), "rb").read()
+    (tmp_path / src).write_bytes(data + b"\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.recorded_traffic(rec[0][0], int(rec[0][1]), int(rec[0][2])) == (None, None)
