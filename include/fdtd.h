@@ -427,7 +427,11 @@ int fdtd_pool_opts_default(fdtd_pool_opts *opts);
    coefficients, and an FP64 staging array when it has host inputs or keep = 1). */
 int fdtd_pool_request_bytes(const fdtd_request *req, size_t *out);
 
-/* Create a pool and start its loop thread. FDTD_E_NOMEM if the budget cannot be allocated. */
+/* Create a pool and start its loop thread. FDTD_E_NOMEM if the budget cannot be allocated.
+   Each batched launch cuts every request into z-chunks of about 64 planes (32 when the
+   launch would have fewer than 512 tiles); FDTD_POOL_CHUNK (8..4096, read once per
+   process) sets the length. The pool also allocates its tile-queue counters (256 bytes)
+   outside the budget. */
 int fdtd_pool_create(const fdtd_pool_opts *opts, fdtd_pool_t *out);
 
 /*

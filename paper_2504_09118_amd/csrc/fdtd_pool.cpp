@@ -135,12 +135,23 @@ struct Req {
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 // z-split of one batched launch. A launch ends with its longest workgroup, so
-// every request is cut into z-chunks of about the same length (kChunk planes;
+// every request is cut into z-chunks of about the same length (pool_chunk() planes;
 // each chunk recomputes 2*tb-1 planes); a launch with fewer than kTargetTiles
 // workgroups halves the length once to fill more CUs. The split never changes
 // a request's bits.
-constexpr int kChunk = 48;
+constexpr int kChunkDefault = 64;
 constexpr int kTargetTiles = 512;
+
+// FDTD_POOL_CHUNK overrides the chunk length (planes, 8..4096; read once).
+int pool_chunk()
+{
+    static const int v = [] {
+        const char *e = getenv("FDTD_POOL_CHUNK");
+        const int c = (e && *e) ? atoi(e) : kChunkDefault;
+        return c < 8 ? 8 : (c > 4096 ? 4096 : c);
+    }();
+    return v;
+}
 
 int zsplit(const Geom &g, int len)
 {
@@ -387,10 +398,10 @@ bool launch_round(fdtd_pool_t p)
         long long tiles_at_chunk = 0;
         for (Req *r : kv.second) {
             int kc, ntx, nty, nt;
-            fdtd::temporal_tiling(r->plan.g, ts, zsplit(r->plan.g, kChunk), &kc, &ntx, &nty, &nt);
+            fdtd::temporal_tiling(r->plan.g, ts, zsplit(r->plan.g, pool_chunk()), &kc, &ntx, &nty, &nt);
             tiles_at_chunk += nt;
         }
-        const int len = tiles_at_chunk < kTargetTiles ? kChunk / 2 : kChunk;
+        const int len = tiles_at_chunk < kTargetTiles ? pool_chunk() / 2 : pool_chunk();
         for (Req *r : kv.second) {
             BatchEntry &e = tab[n++];
             e.g = r->plan.g;
