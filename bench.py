@@ -86,7 +86,9 @@ def main() -> int:
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16", "f16c", "bf16c"],
                     help="device field storage (16-bit fields compute in FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps on the host's CPU share")
+    ap.add_argument("--cpu-steps-1thread", type=int, default=10, help="oracle steps on one thread")
+    ap.add_argument("--numpy-steps", type=int, default=1, help="NumPy slicing-form steps per precision")
     ap.add_argument("--autotune", action="store_true", help="time every built schedule first and keep the fastest")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serving-requests", type=int, default=200)
@@ -132,28 +134,37 @@ def main() -> int:
     q = s.query()
     kernel = q["kernel"]
     steps_per_launch = int(q["steps_per_sweep"])
+    # the bandwidth probe runs before the warm-up steps: it also brings the GPU out of idle
+    probe = copy_probe(stream)
     s.step(args.warmup)
     s.sync()
     torch.cuda.synchronize()
     print(f"[bench] kernel={kernel} steps/sweep={steps_per_launch} warmup done", file=sys.stderr, flush=True)
 
     sweeps_before = s.query()["sweeps"]
-    # the timed steps run as up to 10 equal repetitions (whole sweeps each, the last one takes
-    # the remainder) with an event between repetitions, so the line also carries mean and spread
-    nrep = max(1, min(10, args.steps // steps_per_launch))
-    chunk = args.steps // nrep // steps_per_launch * steps_per_launch
-    chunks = [chunk] * (nrep - 1) + [args.steps - chunk * (nrep - 1)]
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(nrep + 1)]
+    # the timed steps, issued one sweep per call (the temporal schedule: sweeps of tb steps and
+    # one remainder sweep; the other schedules: one step per call) with an event after each
+    # call on the solver's stream, so the dominant kernel's average launch duration comes from
+    # the timed region itself
+    per_call = steps_per_launch if kernel == "temporal" else 1
+    calls = [per_call] * (args.steps // per_call) + ([args.steps % per_call] if args.steps % per_call else [])
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(calls) + 1)]
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     evs[0].record(stream)
-    for r, c in enumerate(chunks):
+    for r, c in enumerate(calls):
         s.step(c)
         evs[r + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = evs[0].elapsed_time(evs[-1])
-    rep_rates = [nx * ny * nz * c / (evs[r].elapsed_time(evs[r + 1]) / 1e3) / 1e9 for r, c in enumerate(chunks)]
+    call_ms = [evs[r].elapsed_time(evs[r + 1]) for r in range(len(calls))]
+    # repetition spread: up to 10 equal groups of whole calls (the last takes the rest)
+    nrep = max(1, min(10, len(calls)))
+    per_rep = len(calls) // nrep
+    groups = [list(range(r * per_rep, (r + 1) * per_rep if r < nrep - 1 else len(calls))) for r in range(nrep)]
+    chunks = [sum(calls[i] for i in g) for g in groups]
+    rep_rates = [nx * ny * nz * c / (sum(call_ms[i] for i in g) / 1e3) / 1e9 for c, g in zip(chunks, groups)]
     sweeps = s.query()["sweeps"] - sweeps_before
     s_sched = s.schedule
     d = s.diag()
@@ -166,15 +177,19 @@ def main() -> int:
     # coefficient arrays once and writes the six components once, whatever its steps per sweep;
     # a plain step is two launches (H sweep, E sweep)
     launches_per_sweep = 2 if kernel == "plain" else 1
-    launches = sweeps * launches_per_sweep
-    avg_launch_s = secs / launches
     b_sweep = algorithmic_bytes_per_cell_step(kernel, q["ce_array"], q["ch_array"],
                                               field_bytes=FIELD_BYTES[args.storage])
     bytes_per_launch = b_sweep * cells / launches_per_sweep
-    achieved = bytes_per_launch * launches / secs / 1e9
+    # the dominant kernel: the full sweeps (calls of per_call steps); a remainder sweep of fewer
+    # steps is a different instantiation and is left out of its average
+    dom = [call_ms[i] for i, c in enumerate(calls) if c == per_call] or call_ms
+    avg_launch_ms = statistics.fmean(dom) / launches_per_sweep
+    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    all_launch_ms = ms / (sweeps * launches_per_sweep)
     traffic, traffic_src = (None, None)
     if nx == ny == nz:
         traffic, traffic_src = recorded_traffic(kernel, steps_per_launch, nx)
+    dtype = "f32" if args.storage == "f32" else f"{args.storage} storage, f32 compute"
 
     result = {
         "metric": f"Gcell-updates/s ({nx}^3 {STORAGE_LABEL[args.storage]} PEC cavity, "
@@ -188,7 +203,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": ("synthetic: 32 seeded spherical inclusions eps_r~U[1,4], E~U[-1,1] (SplitMix64), H=0"
                  if args.workload == "spheres" else
                  "synthetic: vacuum eps_r=mu_r=1 given as arrays, E~U[-1,1] (SplitMix64 seed 2), H=0"),
@@ -200,9 +215,13 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_source": traffic_src,
+                     "kernel": (f"{kernel} sweep of {per_call} steps" if kernel == "temporal" else kernel),
+                     "launches_timed": len(dom) * launches_per_sweep,
                      "bytes_per_cell_step": round(b_sweep / steps_per_launch, 3),
                      "bytes_per_launch": bytes_per_launch,
-                     "avg_launch_ms": round(avg_launch_s * 1e3, 5),
+                     "avg_launch_ms": round(avg_launch_ms, 5),
+                     # every launch of the timed region, remainder sweep included
+                     "avg_launch_ms_all": round(all_launch_ms, 5),
                      # throughput against the single-step HBM roofline (each step moving b_sweep bytes)
                      "frac_of_single_step_roofline": round(gcells / (HBM_PEAK_GBS / b_sweep), 4)},
         "repetitions": {"n": nrep, "steps_each": chunks, "gcells_mean": round(statistics.fmean(rep_rates), 3),
@@ -212,7 +231,7 @@ def main() -> int:
         "energy_check": {"nonfinite": d["nonfinite"], "max_e_tan": d["max_e_tan"]},
     }
 
-    result["copy_probe"] = copy_probe(stream)
+    result["copy_probe"] = probe
     if not args.no_serving:
         from paper_2504_09118_amd import serve
 
@@ -220,12 +239,13 @@ def main() -> int:
                                               n_requests=args.serving_requests, stream=stream,
                                               log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(e, eps, nx, ny, nz, dx, dt, args.cpu_steps)
+        result["cpu_baseline"] = cpu_baseline(e, eps, nx, ny, nz, dx, dt, args.cpu_steps, args.cpu_steps_1thread,
+                                              args.numpy_steps, gpu_gcells=gcells)
     print(json.dumps(result), flush=True)
     return 0
 
 
-def copy_probe(stream, nbytes: int = 2 << 30, reps: int = 10):
+def copy_probe(stream, nbytes: int = 2 << 30, reps: int = 40):
     """Achievable HBM bandwidth: the library's 16-byte streaming copy of 2 GiB (read + write counted)."""
     import torch
 
@@ -248,13 +268,36 @@ def copy_probe(stream, nbytes: int = 2 << 30, reps: int = 10):
             "bytes_written_per_launch": nbytes, "avg_launch_ms": round(ms, 4)}
 
 
-def cpu_baseline(e32, eps, nx, ny, nz, dx, dt, steps):
-    """The FP64 oracle, as it stands, on the full 512^3 state for a few steps on the host cores."""
+def host_cpus():
+    """(threads to use, description): the process's CPU share (OMP_NUM_THREADS when set, else
+    the CPUs it may run on), with the CPU model and the counts the host reports."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or affinity
+    return max(1, min(share, affinity)), {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": affinity}
+
+
+def cpu_baseline(e32, eps, nx, ny, nz, dx, dt, steps, steps1=10, numpy_steps=1, gpu_gcells=None):
+    """The FP64 oracle, as it stands, on the full state of the same workload for a few steps on
+    the host cores (the process's CPU share), then on one thread for steps1 steps; then the
+    paper's own baseline, the NumPy slicing form, single-threaded in FP64 and FP32 for
+    numpy_steps steps each (the paper times NumPy on one thread, Sec. 4)."""
     import numpy as np
 
     import oracle
+    from oracle import numpy_form
 
-    threads = min(16, os.cpu_count() or 1)
+    threads, host = host_cpus()
     oracle.set_threads(threads)
     ce = oracle.coef_e(nx, ny, nz, dx, dt, eps)
     ch = oracle.coef_h(nx, ny, nz, dx, dt)
@@ -263,18 +306,35 @@ def cpu_baseline(e32, eps, nx, ny, nz, dx, dt, steps):
     oracle.run(fields, ce, ch, steps)
     secs = time.perf_counter() - t0
     rate = nx * ny * nz * steps / secs / 1e9
-    # the same oracle on one thread, a shorter sample of the same state
-    steps1 = max(1, steps // 30)
     oracle.set_threads(1)
     t1 = time.perf_counter()
     oracle.run(fields, ce, ch, steps1)
     secs1 = time.perf_counter() - t1
     oracle.set_threads(threads)
     rate1 = nx * ny * nz * steps1 / secs1 / 1e9
-    return {"value": round(rate, 5), "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"full {nx}x{ny}x{nz} cavity, same inputs, {steps} leapfrog steps in FP64 "
-                      f"({secs:.1f}s); one thread: {steps1} more steps ({secs1:.1f}s)",
-            "value_1thread": round(rate1, 5)}
+    out = {"value": round(rate, 5), "unit": "Gcell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"full {nx}x{ny}x{nz} cavity, same inputs, {steps} leapfrog steps in FP64 on {threads} "
+                     f"threads ({secs:.1f}s); one thread: {steps1} more steps ({secs1:.1f}s)",
+           "value_1thread": round(rate1, 5), "steps": steps, "steps_1thread": steps1, **host}
+    # NumPy slicing form (its array operations run on one thread), FP64 then FP32
+    numpy_rates = {}
+    for name, dtp in (("f64", np.float64), ("f32", np.float32)):
+        f = [a.astype(dtp) for a in fields]
+        c_e = [a.astype(dtp) for a in ce]
+        c_h = [a.astype(dtp) for a in ch]
+        t2 = time.perf_counter()
+        numpy_form.run(f, c_e, c_h, numpy_steps)
+        numpy_rates[name] = nx * ny * nz * numpy_steps / (time.perf_counter() - t2) / 1e9
+        del f, c_e, c_h
+    out["numpy"] = {"gcells_f64": round(numpy_rates["f64"], 6), "gcells_f32": round(numpy_rates["f32"], 6),
+                    "threads": 1, "steps": numpy_steps,
+                    "sample": f"the paper's NumPy slicing form on the full {nx}x{ny}x{nz} state, {numpy_steps} "
+                              f"step(s) per precision, one thread"}
+    if gpu_gcells:
+        out["numpy"]["gpu_over_numpy_f32"] = round(gpu_gcells / numpy_rates["f32"], 1)
+        out["numpy"]["gpu_over_numpy_f64"] = round(gpu_gcells / numpy_rates["f64"], 1)
+        out["numpy"]["paper_mlir_over_numpy"] = "5.14x (64^3) to 8.56x (1024^3), FP32, one CPU thread (Sec. 5)"
+    return out
 
 
 if __name__ == "__main__":

@@ -152,7 +152,10 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
  * (round_up(nx+1, 64) * (ny+1) values) below 2^31 bytes (FDTD_E_ARG);
  * dx, dt finite and > 0; every material value
  * finite and > 0; the Courant limit dt*sqrt(3)/dx < sqrt(min eps_r * min mu_r)
- * (FDTD_E_CFL); arena large enough (FDTD_E_NOMEM). Host arrays in coef are
+ * (FDTD_E_CFL); a given arena of at least fdtd_required_bytes, and without
+ * an arena a need within the byte count in the environment variable
+ * FDTD_HBM_BUDGET when it is set (FDTD_E_NOMEM; both checked before any
+ * device call, then FDTD_E_NOMEM if hipMalloc fails). Host arrays in coef are
  * read during the call only. The arena, if given, is borrowed until
  * fdtd_destroy and must stay allocated. *out is set only on FDTD_OK.
  * Environment overrides read here (tuning and test aids; none changes the
@@ -198,6 +201,8 @@ int fdtd_init_random(fdtd_t h, unsigned long long seed);
 /*
  * Enqueue n >= 0 leapfrog steps (Sec. 2.1 algorithm listing: H update, H
  * boundary, E update, E boundary). Asynchronous: returns after launching.
+ * The temporal schedule runs floor(n / tb) sweeps of tb steps and then one
+ * sweep of n mod tb steps (16-bit storage rounds the state once per sweep).
  * Launch failures return FDTD_E_DEVICE at once; faults during execution
  * surface at the next fdtd_sync / fdtd_get_fields. The temporal sweeps hand
  * out tiles from counters in the solver's arena, which every launch leaves at
@@ -456,11 +461,13 @@ int fdtd_pool_info(fdtd_pool_t pool, long long id, fdtd_request_info *out);
 /*
  * Copy the final state (E^n, H^{n-1/2}) of a done keep = 1 request into six
  * host arrays (host layout, FDTD_F32 or FDTD_F64); waits for the copy. The
- * request stays resident until fdtd_pool_release.
+ * request stays resident until fdtd_pool_release. Thread-safe: while a fetch
+ * of a request runs, fdtd_pool_release of the same id returns FDTD_E_STATE.
  */
 int fdtd_pool_fetch(fdtd_pool_t pool, long long id, void *const host[6], int host_dtype);
 
-/* Free a request's memory (done requests) or cancel it (queued). FDTD_E_STATE while admitted and running. */
+/* Free a request's memory (done requests) or cancel it (queued). FDTD_E_STATE while admitted and
+ * running, or while a fetch of it is in progress. Thread-safe. */
 int fdtd_pool_release(fdtd_pool_t pool, long long id);
 
 /* Counters of the pool. Thread-safe. */

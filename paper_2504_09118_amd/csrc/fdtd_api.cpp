@@ -304,27 +304,25 @@ hipError_t launch_one(fdtd_t h, int kernel, int ts)
 template <typename T>
 int step_impl(fdtd_t h, long long n)
 {
-    // temporal: floor(n / tb) sweeps of tb steps, the remainder as single-step slab sweeps
-    // (the same bits either way)
-    long long sweeps_tb = 0, singles = n;
-    if (h->kernel == FDTD_KERNEL_TEMPORAL) {
-        sweeps_tb = n / h->tb;
-        singles = n % h->tb;
-    }
-    for (long long s = 0; s < sweeps_tb; ++s) {
-        hipError_t e = launch_one<T>(h, FDTD_KERNEL_TEMPORAL, h->tb);
+    // temporal: floor(n / tb) sweeps of tb steps, then the remainder as ONE sweep of n mod tb
+    // steps (FP32: the same bits as single steps; 16-bit storage rounds the state once per
+    // sweep, so a remainder sweep rounds once, as the serving pool's last round does);
+    // other schedules: one launch per step
+    const long long tb = h->kernel == FDTD_KERNEL_TEMPORAL ? h->tb : 1;
+    const long long full = n / tb;
+    const int rest = (int)(n % tb);
+    for (long long s = 0; s < full; ++s) {
+        hipError_t e = launch_one<T>(h, h->kernel, (int)tb);
         if (e != hipSuccess)
             return device_fail(h, e, "kernel launch");
-        h->steps += h->tb;
+        h->steps += tb;
         h->sweeps += 1;
     }
-    // single steps: the slab sweep (the temporal sweep with ts = 1 for 16-bit storage)
-    const int single_kernel = h->kernel == FDTD_KERNEL_TEMPORAL ? FDTD_KERNEL_SLAB : h->kernel;
-    for (long long s = 0; s < singles; ++s) {
-        hipError_t e = launch_one<T>(h, single_kernel, 1);
+    if (rest > 0) {
+        hipError_t e = launch_one<T>(h, FDTD_KERNEL_TEMPORAL, rest);
         if (e != hipSuccess)
             return device_fail(h, e, "kernel launch");
-        h->steps += 1;
+        h->steps += rest;
         h->sweeps += 1;
     }
     return FDTD_OK;
@@ -568,6 +566,15 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
                     std::sqrt(eps_min * mu_min));
 
     Plan p = make_plan(nx, ny, nz, o->storage, eps != nullptr || rect, mu != nullptr || rect);
+    // memory limits are checked before any device call
+    const size_t need = p.total + 256;
+    if (o->arena && o->arena_bytes < need)
+        return fail(FDTD_E_NOMEM, "arena of %zu bytes < required %zu", o->arena_bytes, need);
+    if (!o->arena) {
+        const char *budget = getenv("FDTD_HBM_BUDGET");
+        if (budget && *budget && (double)need > atof(budget))
+            return fail(FDTD_E_NOMEM, "required %zu bytes exceed FDTD_HBM_BUDGET=%s", need, budget);
+    }
     hipError_t e = hipSetDevice(o->device);
     if (e != hipSuccess)
         return fail(FDTD_E_DEVICE, "hipSetDevice(%d): %s", o->device, hipGetErrorString(e));
@@ -656,31 +663,20 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     }
     char *base;
     if (o->arena) {
-        if (o->arena_bytes < p.total + 256) {
-            if (h->own_stream) (void)hipStreamDestroy(h->stream);
-            delete h;
-            return fail(FDTD_E_NOMEM, "arena of %zu bytes < required %zu", o->arena_bytes, p.total + 256);
-        }
         h->arena = (char *)o->arena;
         h->arena_bytes = o->arena_bytes;
         h->own_arena = false;
     } else {
-        const char *budget = getenv("FDTD_HBM_BUDGET");
-        if (budget && *budget && (double)(p.total + 256) > atof(budget)) {
-            if (h->own_stream) (void)hipStreamDestroy(h->stream);
-            delete h;
-            return fail(FDTD_E_NOMEM, "required %zu bytes exceed FDTD_HBM_BUDGET=%s", p.total + 256, budget);
-        }
         void *mem = nullptr;
-        e = hipMalloc(&mem, p.total + 256);
+        e = hipMalloc(&mem, need);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             if (h->own_stream) (void)hipStreamDestroy(h->stream);
             delete h;
-            return fail(FDTD_E_NOMEM, "hipMalloc(%zu): %s", p.total + 256, hipGetErrorString(e));
+            return fail(FDTD_E_NOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
         }
         h->arena = (char *)mem;
-        h->arena_bytes = p.total + 256;
+        h->arena_bytes = need;
         h->own_arena = true;
     }
     base = (char *)round_up((uintptr_t)h->arena, 256);

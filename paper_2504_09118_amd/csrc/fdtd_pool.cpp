@@ -130,6 +130,7 @@ struct Req {
     int cur;
     hipEvent_t done_ev;
     bool ev_live;  // done_ev created and not yet destroyed
+    int fetching;  // fdtd_pool_fetch calls reading this request's memory now (release refuses)
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
@@ -819,10 +820,16 @@ int fdtd_pool_fetch(fdtd_pool_t p, long long id, void *const host[6], int host_d
             return pfail(FDTD_E_STATE, "request %lld was not submitted with keep = 1", id);
         if (r->state != FDTD_REQ_DONE)
             return pfail(FDTD_E_STATE, "request %lld is not done (state %d)", id, r->state);
+        // pinned while its memory is read outside the lock: a concurrent release refuses
+        r->fetching += 1;
     }
     hipError_t e = hipSetDevice(p->device);
     if (e == hipSuccess)
         e = host_dtype == FDTD_F32 ? fetch_fields<float>(p, *r, host) : fetch_fields<double>(p, *r, host);
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        r->fetching -= 1;
+    }
     if (e != hipSuccess)
         return pfail(FDTD_E_DEVICE, "fetch: %s", hipGetErrorString(e));
     return FDTD_OK;
@@ -838,6 +845,8 @@ int fdtd_pool_release(fdtd_pool_t p, long long id)
         return pfail(FDTD_E_ARG, "unknown request id %lld", id);
     if (r->state == FDTD_REQ_ACTIVE)
         return pfail(FDTD_E_STATE, "request %lld is running", id);
+    if (r->fetching > 0)
+        return pfail(FDTD_E_STATE, "request %lld is being fetched", id);
     if (r->state == FDTD_REQ_QUEUED)
         p->queue.erase(std::find(p->queue.begin(), p->queue.end(), r));
     if (r->region_held) {

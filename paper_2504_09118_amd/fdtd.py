@@ -310,17 +310,29 @@ class Solver:
         ptrs = (ctypes.c_void_p * 6)(*[a.ctypes.data for a in keep])
         _check(self._lib.fdtd_set_fields(self._h, ptrs, _dtype_code(dt)))
 
-    def set_fields_device(self, tensors):
-        """Set the state from six contiguous torch CUDA tensors (float32/float64, host layout shapes)."""
+    def _device_tensors_code(self, tensors) -> int:
+        """Check six device tensors against the field layout (before any launch touches them)
+        and return their dtype code: GPU tensors, contiguous, one dtype (float32 or float64),
+        exactly the host-layout field shapes."""
         import torch
 
+        if len(tensors) != 6:
+            raise ValueError("six tensors (Ex, Ey, Ez, Hx, Hy, Hz) are required")
         dt = tensors[0].dtype
+        if dt not in (torch.float32, torch.float64):
+            raise ValueError(f"unsupported dtype {dt}: float32 or float64 only")
         for t, s in zip(tensors, self.shapes):
+            if not isinstance(t, torch.Tensor):
+                raise ValueError("device buffers must be torch tensors")
             if tuple(t.shape) != s or not t.is_contiguous() or t.dtype != dt:
                 raise ValueError("device tensors must be contiguous, of one dtype, with the field shapes")
-        code = F32 if dt == torch.float32 else F64 if dt == torch.float64 else None
-        if code is None:
-            raise ValueError(f"unsupported dtype {dt}")
+        if any(t.device.type != "cuda" for t in tensors):
+            raise ValueError("device tensors must live on the GPU")
+        return F32 if dt == torch.float32 else F64
+
+    def set_fields_device(self, tensors):
+        """Set the state from six contiguous torch CUDA tensors (float32/float64, host layout shapes)."""
+        code = self._device_tensors_code(tensors)
         ptrs = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in tensors])
         _check(self._lib.fdtd_set_fields_device(self._h, ptrs, code))
 
@@ -337,10 +349,7 @@ class Solver:
 
     def get_fields_device(self, tensors):
         """Write the state into six contiguous torch CUDA tensors (enqueued, no wait)."""
-        import torch
-
-        dt = tensors[0].dtype
-        code = F32 if dt == torch.float32 else F64
+        code = self._device_tensors_code(tensors)
         ptrs = (ctypes.c_void_p * 6)(*[t.data_ptr() for t in tensors])
         _check(self._lib.fdtd_get_fields_device(self._h, ptrs, code))
 

@@ -270,3 +270,67 @@ def test_recorded_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     (tmp_path / src).write_bytes(data + b"\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.recorded_traffic(rec[0][0], int(rec[0][1]), int(rec[0][2])) == (None, None)
+
+
+def _create_with(nx=32, ny=32, nz=32, arena=None, arena_bytes=0):
+    lib = F.load_library()
+    coef = F._Coef()
+    opts = F._Opts()
+    lib.fdtd_opts_default(ctypes.byref(opts))
+    opts.arena = arena
+    opts.arena_bytes = arena_bytes
+    h = ctypes.c_void_p(None)
+    st = lib.fdtd_create(nx, ny, nz, 1.0, 0.25, ctypes.byref(coef), ctypes.byref(opts), ctypes.byref(h))
+    return st, h
+
+
+def test_create_rejects_an_arena_smaller_than_required():
+    # checked before any device call: the arena pointer is never touched
+    need = F.required_bytes(32, 32, 32)
+    st, h = _create_with(arena=0x10000, arena_bytes=need - 1)
+    assert st == F.E_NOMEM and not h.value
+    assert b"arena" in F.load_library().fdtd_last_error()
+
+
+def test_create_respects_the_hbm_budget(monkeypatch):
+    need = F.required_bytes(32, 32, 32)
+    monkeypatch.setenv("FDTD_HBM_BUDGET", str(need - 1))
+    st, h = _create_with()
+    assert st == F.E_NOMEM and not h.value
+    assert b"FDTD_HBM_BUDGET" in F.load_library().fdtd_last_error()
+    # a budget that covers the need passes the check (and then needs a device)
+    monkeypatch.setenv("FDTD_HBM_BUDGET", str(need))
+    st, h = _create_with()
+    assert st != F.E_NOMEM
+    if st == F.OK:
+        F.load_library().fdtd_destroy(h)
+
+
+def test_device_tensor_checks_refuse_wrong_buffers_before_any_launch():
+    """get_fields_device / set_fields_device validate shapes, contiguity, dtype and device
+    in the binding, so a wrong tensor never reaches a kernel (no GPU needed for the refusal)."""
+    import torch
+
+    class Fake:
+        shapes = F.field_shapes(6, 5, 4)
+
+    check = F.Solver._device_tensors_code
+    good = [torch.zeros(s, dtype=torch.float32) for s in Fake.shapes]
+    with pytest.raises(ValueError, match="GPU"):
+        check(Fake(), good)  # right layout, but host memory
+    small = list(good)
+    small[2] = torch.zeros((1, 1, 1), dtype=torch.float32)
+    with pytest.raises(ValueError, match="shapes"):
+        check(Fake(), small)
+    strided = list(good)
+    strided[4] = torch.zeros(Fake.shapes[4][::-1], dtype=torch.float32).permute(2, 1, 0)
+    with pytest.raises(ValueError, match="contiguous"):
+        check(Fake(), strided)
+    mixed = list(good)
+    mixed[5] = mixed[5].double()
+    with pytest.raises(ValueError, match="one dtype"):
+        check(Fake(), mixed)
+    with pytest.raises(ValueError, match="float32 or float64"):
+        check(Fake(), [t.half() for t in good])
+    with pytest.raises(ValueError, match="six"):
+        check(Fake(), good[:5])

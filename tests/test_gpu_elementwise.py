@@ -1,0 +1,120 @@
+"""Element-wise checks of the device state against the FP32 model of its update rule.
+
+tests/fp32_fma.py evaluates Eq. 2 exactly as the device rounds it (FP32
+differences, one fused multiply-add per component) and, for 16-bit storage,
+rounds the state after each sweep as the device stores it. Both are
+deterministic, so the device state must equal the model node by node: no
+error norm stands between the two. This covers the sweep's store path for
+every storage type (the packed 16-bit conversions, the compensated encoder
+and its residual bytes) and the remainder sweep of a step count that is not
+a multiple of the steps per sweep.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import cavity_inputs as ci
+import oracle
+from tests import fp32_fma
+from tests.test_gpu_precision import round_store
+
+pytestmark = pytest.mark.gpu
+
+S = 0.5 / math.sqrt(3.0)
+DIMS = (150, 61, 37)   # 3 x 3 temporal tiles of 64 x 22 own cells, ragged in x and y
+
+
+def model_inputs(nx, ny, nz, seed, store):
+    eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=6)
+    e = ci.random_e(nx, ny, nz, seed=seed, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=seed + 1, dtype=np.float32)
+    start = oracle.make_state([store(a).astype(np.float64) for a in e], [store(a).astype(np.float64) for a in h])
+    start = [a.astype(np.float32) for a in start]
+    ce = [a.astype(np.float32) for a in oracle.round_to(oracle.coef_e(nx, ny, nz, 1.0, S, eps), np.float32)]
+    ch = [a.astype(np.float32) for a in oracle.round_to(oracle.coef_h(nx, ny, nz, 1.0, S), np.float32)]
+    return eps, e, h, start, ce, ch
+
+
+def steps_of_storage(storage):
+    if storage == "f32":
+        return lambda a: np.asarray(a, dtype=np.float32)
+    return lambda a: round_store(a, storage).astype(np.float32)
+
+
+def residual_step(x, storage):
+    """The value spacing of a compensated store near x (ulp of the 16-bit part / 256)."""
+    x = np.asarray(x, dtype=np.float32)
+    if storage == "f16c":
+        hi = x.astype(np.float16)
+        e = np.maximum((hi.view(np.uint16).astype(np.int64) >> 10) & 0x1F, 1)
+        return np.ldexp(1.0, e - 15 - 10 - 8)
+    hi = round_store(x, "bf16").astype(np.float32)
+    e = np.maximum((hi.view(np.uint32).astype(np.int64) >> 23) & 0xFF, 16)
+    return np.ldexp(1.0, e - 127 - 7 - 8)
+
+
+def ulp16(x, storage):
+    x = np.asarray(x, dtype=np.float32)
+    if storage == "f16":
+        return np.spacing(np.abs(x.astype(np.float16))).astype(np.float64)
+    hi = np.abs(round_store(x, "bf16")).astype(np.float32)
+    e = np.maximum((hi.view(np.uint32).astype(np.int64) >> 23) & 0xFF, 1)
+    return np.ldexp(1.0, e - 127 - 7)
+
+
+@pytest.mark.parametrize("kernel,tb,steps", [("auto", 0, 20), ("temporal", 2, 7), ("slab", 0, 5),
+                                             ("plain", 0, 5)])
+def test_fp32_state_equals_the_fma_model(kernel, tb, steps):
+    """FP32 storage: the device state after several steps equals the model bit for bit."""
+    from paper_2504_09118_amd import Solver
+
+    nx, ny, nz = DIMS
+    store = steps_of_storage("f32")
+    eps, e, h, start, ce, ch = model_inputs(nx, ny, nz, 41, store)
+    with Solver(nx, ny, nz, 1.0, S, eps_r=eps, kernel=kernel, tb_steps=tb) as s:
+        s.set_fields(e, h)
+        s.step(steps)
+        got = s.get_fields(np.float32)
+    model = [a.copy() for a in start]
+    fp32_fma.run_sweeps(model, ce, ch, steps, 1)
+    for name, g, m in zip(("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"), got, model):
+        bad = int(np.sum(g != m))
+        assert bad == 0, f"{name}: {bad} nodes differ from the FP32 model (max |diff| {np.max(np.abs(g - m)):.3e})"
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16", "f16c", "bf16c"])
+@pytest.mark.parametrize("steps", [3, 5])
+def test_16bit_sweeps_equal_the_storage_model(storage, steps):
+    """16-bit storage: one sweep of 3 steps (and a second, remainder sweep of 2) from a
+    16-bit state, node by node against the model that rounds the FP32 state once per sweep.
+    Every node must lie within one storage step (one 16-bit ulp, or one residual step for the
+    compensated types) and all but a vanishing share must be equal."""
+    from paper_2504_09118_amd import Solver
+
+    nx, ny, nz = DIMS
+    store = steps_of_storage(storage)
+    eps, e, h, start, ce, ch = model_inputs(nx, ny, nz, 43, store)
+    with Solver(nx, ny, nz, 1.0, S, eps_r=eps, storage=storage, kernel="temporal", tb_steps=3) as s:
+        s.set_fields(e, h)
+        s.step(steps)
+        assert s.query()["sweeps"] == (1 if steps == 3 else 2)
+        got = s.get_fields(np.float32)
+    # the initial state on the device is the model's start
+    model = [a.copy() for a in start]
+    fp32_fma.run_sweeps(model, ce, ch, steps, 3, store=store)
+    total, bad, worst = 0, 0, 0.0
+    for name, g, m in zip(("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"), got, model):
+        diff = np.abs(g.astype(np.float64) - m.astype(np.float64))
+        if storage.endswith("c"):
+            unit = np.maximum(residual_step(g, storage), residual_step(m, storage))
+        else:
+            unit = np.maximum(ulp16(g, storage), ulp16(m, storage))
+        total += g.size
+        bad += int(np.sum(diff > 0))
+        worst = max(worst, float(np.max(diff / unit)))
+    print(f"\n{storage}, {steps} steps: {bad} of {total} nodes differ from the storage model; "
+          f"largest difference {worst:.3g} storage steps")
+    assert worst <= 1.0
+    assert bad <= max(2, total // 100000)

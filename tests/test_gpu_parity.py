@@ -141,7 +141,8 @@ def test_parity_ragged_medium(kernel):
 
 
 def test_kernels_bitwise_equal(monkeypatch):
-    nx, ny, nz, steps = 70, 19, 37, 40
+    # 41 steps: tb = 3 leaves a remainder sweep of 2 steps, tb = 2 one of 1
+    nx, ny, nz, steps = 70, 19, 37, 41
     eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=8)
     e = ci.random_e(nx, ny, nz, seed=5, dtype=np.float32)
     h = ci.random_h(nx, ny, nz, seed=6, dtype=np.float32)
@@ -488,3 +489,75 @@ def test_schedule_changes_between_sweeps_keep_the_bits():
         got = s.get_fields()
     for x, y in zip(got, plain):
         assert np.array_equal(x, y)
+
+
+def test_full_size_default_schedule_equals_plain_bitwise():
+    """512^3 with spherical inclusions, the benchmark's launch configuration (temporal
+    sweeps of 3 steps from the per-XCD tile queues, 4 z-chunks), 32 steps (ten 3-step sweeps
+    and a 2-step remainder sweep): the whole state equals the plain two-kernel schedule bit
+    for bit. Both runs stay on the GPU; the comparison runs there too."""
+    import torch
+
+    from paper_2504_09118_amd import Solver, field_shapes
+
+    n, steps = 512, 32
+    eps = ci.sphere_eps(n, n, n, seed=33)
+    stream = torch.cuda.Stream()
+    outs = {}
+    for kernel in ("auto", "plain"):
+        with Solver(n, n, n, 1.0, S, eps_r=eps, kernel=kernel, stream=stream) as s:
+            s.init_random(3)
+            s.step(steps)
+            q = s.query()
+            if kernel == "auto":
+                assert q["kernel"] == "temporal" and q["steps_per_sweep"] == 3 and q["sweeps"] == 11
+            out = [torch.empty(sh, dtype=torch.float32, device="cuda") for sh in field_shapes(n, n, n)]
+            s.get_fields_device(out)
+            s.sync()
+            outs[kernel] = out
+    for name, a, b in zip(("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"), outs["auto"], outs["plain"]):
+        # bitwise, -0 and +0 included
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32)), name
+    assert float(outs["auto"][0].abs().max()) > 0
+
+
+def test_destroyed_handle_is_rejected():
+    """Every call on a handle after fdtd_destroy returns FDTD_E_STATE (the handle is no
+    longer live, so nothing behind it is read)."""
+    import ctypes
+
+    from paper_2504_09118_amd import fdtd as F
+
+    lib = F.load_library()
+    s = _solver(16, 12, 10, 1.0, S)
+    h = ctypes.c_void_p(s._h.value)
+    assert lib.fdtd_destroy(h) == F.OK
+    s._h = ctypes.c_void_p(None)  # the wrapper no longer owns it
+    ptrs = (ctypes.c_void_p * 6)()
+    out = (ctypes.c_double * 6)()
+    assert lib.fdtd_step(h, 1) == F.E_STATE
+    assert lib.fdtd_sync(h) == F.E_STATE
+    assert lib.fdtd_get_fields(h, ptrs, F.F32) == F.E_STATE
+    assert lib.fdtd_set_fields(h, ptrs, F.F32) == F.E_STATE
+    assert lib.fdtd_diag(h, out) == F.E_STATE
+    assert lib.fdtd_steps_done(h) == -1
+    assert lib.fdtd_destroy(h) == F.E_STATE
+
+
+@pytest.mark.parametrize("kernel", ["auto", "slab"])
+def test_nan_input_is_counted_by_diag(kernel):
+    """A NaN placed in the state through set_fields spreads by the stencil and is counted by
+    fdtd_diag's non-finite count after one step; the walls stay exactly zero."""
+    nx, ny, nz = 40, 30, 20
+    e = [a.copy() for a in ci.random_e(nx, ny, nz, seed=9, dtype=np.float32)]
+    e[1][10, 12, 15] = np.nan   # an interior Ey node: [k, j, i]
+    with _solver(nx, ny, nz, 1.0, S, kernel=kernel) as s:
+        s.set_fields(e)
+        assert s.diag()["nonfinite"] == 1
+        s.step(1)
+        d = s.diag()
+        got = s.get_fields(np.float32)
+    assert d["nonfinite"] > 1
+    assert np.isnan(got[1][10, 12, 15])
+    assert d["nonfinite"] == sum(int(np.sum(~np.isfinite(a))) for a in got)
+    assert oracle.tangential_max([np.nan_to_num(a) for a in got]) == 0.0

@@ -96,6 +96,9 @@ CASES = [
     ((32, 32, 32), 100, 3, "bf16c", 1e-4),
     ((32, 32, 32), 1000, 3, "f16c", 3e-5),
     ((32, 32, 32), 1000, 3, "bf16c", 3e-4),
+    # 101 = 33 x 3 + 2: the last sweep is a 2-step remainder sweep (one rounding)
+    ((32, 32, 32), 101, 3, "f16", 2e-3),
+    ((32, 32, 32), 101, 3, "bf16c", 1e-4),
 ]
 
 

@@ -249,3 +249,64 @@ def test_poisson_stream_reports_percentiles():
     for r in (burst, res):
         assert r["requests"] > 0 and 0 < r["p50_ms"] <= r["p99_ms"] <= r["max_ms"]
         assert r["gcell_per_s"] > 0
+
+
+def test_requests_joining_a_running_batch_keep_their_bits():
+    """Continuous batching under a binding budget: requests submitted while others are on
+    the GPU (staggered arrivals from a second thread) are admitted as memory frees up and
+    join launches already running for others. Every result equals the same request run
+    alone in a pool and a standalone temporal solver, bit for bit."""
+    import threading
+    import time
+
+    P = _pkg()
+    specs = [
+        dict(nx=160, ny=144, nz=128, steps=300, seed=31),
+        dict(nx=112, ny=96, nz=144, steps=251, seed=32, eps="spheres"),
+        dict(nx=144, ny=160, nz=96, steps=202, seed=33),
+        dict(nx=96, ny=128, nz=112, steps=301, seed=34, eps="spheres"),
+        dict(nx=128, ny=80, nz=160, steps=250, seed=35),
+        dict(nx=160, ny=112, nz=96, steps=199, seed=36),
+    ]
+    mats = [materials(sp) for sp in specs]
+    per = max(P.Pool.request_bytes(sp["nx"], sp["ny"], sp["nz"], eps_r=m[0] is not None, keep=True)
+              for sp, m in zip(specs, mats))
+    budget = int(2.6 * per)  # two or three requests resident at once
+    ids = [None] * len(specs)
+    errors = []
+    with P.Pool(budget) as pool:
+        def submitter():
+            try:
+                for q, (sp, m) in enumerate(zip(specs, mats)):
+                    ids[q] = submit(pool, sp, mats=m)
+                    time.sleep(0.004)
+            except Exception as exc:  # reported by the main thread
+                errors.append(exc)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        results = {}
+        for q in range(len(specs)):
+            while ids[q] is None and not errors:
+                time.sleep(0.001)
+            assert not errors, errors
+            pool.wait(ids[q], timeout=120)
+            results[q] = fetch(pool, ids[q], specs[q])
+            pool.release(ids[q])  # frees memory for the requests still queued
+        th.join()
+        infos = [pool.info(i) for i in ids]
+        st = pool.stats()
+    assert st["completed"] == len(specs) and st["bytes_peak"] <= budget
+    # some request was admitted while another one was already running: it joined a batch in flight
+    joined = [q for q in range(len(specs)) for r in range(len(specs))
+              if r != q and infos[r]["t_admit"] < infos[q]["t_admit"] < infos[r]["t_done"]]
+    assert joined, infos
+    # and some request had to wait for memory (admission bound)
+    assert any(x["t_admit"] - x["t_submit"] > 0.002 for x in infos), infos
+    for q, sp in enumerate(specs):
+        with P.Pool(budget) as alone:
+            r = submit(alone, sp, mats=mats[q])
+            alone.wait(r, timeout=120)
+            solo = fetch(alone, r, sp)
+        assert_same(results[q], solo, f"request {q} joined mid-flight vs alone")
+        assert_same(results[q], solo_solver(sp), f"request {q} joined mid-flight vs solver")

@@ -216,6 +216,33 @@ def test_coefficient_single_inclusion(oracle_mod):
     assert ce[2][2, 1, 2] == 0.5 and ce[1][3, 1, 3] == 0.5
 
 
+def test_coefficient_single_mu_inclusion(oracle_mod):
+    # one cell of mu = 5 in vacuum: exactly its 6 faces change, each to dt/(dx * 3) (the mean
+    # of 1 and 5 over the two cells sharing a face); wall-normal faces keep 0
+    nx, ny, nz = 4, 4, 4
+    mu = np.ones((nz, ny, nx))
+    mu[2, 1, 2] = 5.0                      # cell (i, j, k) = (2, 1, 2)
+    ch = oracle.coef_h(nx, ny, nz, 1.0, 1.0, mu)
+    base = oracle.coef_h(nx, ny, nz, 1.0, 1.0)
+    third = 1.0 / 3.0
+    changed = [(f, tuple(int(v) for v in idx)) for f, (a, b) in enumerate(zip(ch, base))
+               for idx in zip(*np.nonzero(a != b))]
+    # arrays are indexed [k, j, i]; Hx(i) is the face between cells i-1 and i
+    assert sorted(changed) == sorted([(0, (2, 1, 2)), (0, (2, 1, 3)),    # Hx at i = 2, 3
+                                      (1, (2, 1, 2)), (1, (2, 2, 2)),    # Hy at j = 1, 2
+                                      (2, (2, 1, 2)), (2, (3, 1, 2))])   # Hz at k = 2, 3
+    for f, idx in changed:
+        assert ch[f][idx] == third
+    # a cell on the x = 0 wall: its wall face stays 0, the five others change
+    mu = np.ones((nz, ny, nx))
+    mu[1, 2, 0] = 5.0                      # cell (0, 2, 1)
+    ch = oracle.coef_h(nx, ny, nz, 1.0, 1.0, mu)
+    changed = sorted((f, tuple(int(v) for v in idx)) for f, (a, b) in enumerate(zip(ch, base))
+                     for idx in zip(*np.nonzero(a != b)))
+    assert changed == sorted([(0, (1, 2, 1)), (1, (1, 2, 0)), (1, (1, 3, 0)), (2, (1, 2, 0)), (2, (2, 2, 0))])
+    assert ch[0][1, 2, 0] == 0.0 and all(ch[f][i] == third for f, i in changed)
+
+
 def test_splitmix64_published_sequence():
     # first outputs of SplitMix64 seeded with 0 (the published generator's stream)
     out = ci.splitmix64(0, np.arange(3, dtype=np.uint64))
