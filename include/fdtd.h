@@ -213,6 +213,22 @@ int fdtd_init_random(fdtd_t h, unsigned long long seed);
 int fdtd_step(fdtd_t h, long long n);
 
 /*
+ * fdtd_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops and harnesses that forbid allocation): the same
+ * steps with the same bits, but the temporal sweeps take their scheduling
+ * counters from a 256-byte array in the library's own device memory (one per
+ * GPU, set up on the first call on that GPU) instead of the solver's arena,
+ * which this call never touches beyond the field and coefficient boxes. It
+ * calls no allocating routine. The counters are cleared by a small kernel on
+ * the solver's stream at the start of every call (no hipMemsetAsync, so the
+ * call can be captured). Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other solvers) race and must be
+ * ordered by the caller. Errors as fdtd_step (FDTD_E_DEVICE if the array's
+ * address cannot be looked up).
+ */
+int fdtd_step_noalloc(fdtd_t h, long long n);
+
+/*
  * Copy the current state (E^n, H^{n-1/2}) into six host arrays of type
  * host_dtype in the host layout above; waits for all enqueued work.
  */

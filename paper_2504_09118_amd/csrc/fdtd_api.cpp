@@ -275,7 +275,7 @@ int env_int(const char *name, int dflt)
 }
 
 template <typename T>
-hipError_t launch_one(fdtd_t h, int kernel, int ts)
+hipError_t launch_one(fdtd_t h, int kernel, int ts, unsigned *queue)
 {
     const auto c = coefs_of<T>(h);
     hipError_t e;
@@ -283,7 +283,7 @@ hipError_t launch_one(fdtd_t h, int kernel, int ts)
         // 16-bit storage is built for the temporal sweep only (ts = 1 for single steps)
         (void)kernel;
         e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                          h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores, h->sched);
+                                          h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores, queue);
     } else {
         if (kernel == FDTD_KERNEL_PLAIN)
             return fdtd::launch_plain_step<T>(h->plan.g, fields_of<T>(h, h->cur), c, h->stream);
@@ -292,7 +292,7 @@ hipError_t launch_one(fdtd_t h, int kernel, int ts)
                                           h->zchunk, h->variant, h->stream, h->nt_stores);
         else if (kernel == FDTD_KERNEL_TEMPORAL)
             e = fdtd::launch_temporal_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
-                                              h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores, h->sched);
+                                              h->tzchunk, ts, h->tvariant, h->stream, h->nt_stores, queue);
         else
             e = fdtd::launch_fused_step<T>(h->plan.g, fields_of<T>(h, h->cur), fields_of<T>(h, 1 - h->cur), c,
                                            h->zchunk, h->stream);
@@ -302,7 +302,7 @@ hipError_t launch_one(fdtd_t h, int kernel, int ts)
 }
 
 template <typename T>
-int step_impl(fdtd_t h, long long n)
+int step_impl(fdtd_t h, long long n, unsigned *queue)
 {
     // temporal: floor(n / tb) sweeps of tb steps, then the remainder as ONE sweep of n mod tb
     // steps (FP32: the same bits as single steps; 16-bit storage rounds the state once per
@@ -312,14 +312,14 @@ int step_impl(fdtd_t h, long long n)
     const long long full = n / tb;
     const int rest = (int)(n % tb);
     for (long long s = 0; s < full; ++s) {
-        hipError_t e = launch_one<T>(h, h->kernel, (int)tb);
+        hipError_t e = launch_one<T>(h, h->kernel, (int)tb, queue);
         if (e != hipSuccess)
             return device_fail(h, e, "kernel launch");
         h->steps += tb;
         h->sweeps += 1;
     }
     if (rest > 0) {
-        hipError_t e = launch_one<T>(h, FDTD_KERNEL_TEMPORAL, rest);
+        hipError_t e = launch_one<T>(h, FDTD_KERNEL_TEMPORAL, rest, queue);
         if (e != hipSuccess)
             return device_fail(h, e, "kernel launch");
         h->steps += rest;
@@ -439,6 +439,17 @@ int get_common(fdtd_t h, void *const dst[6], int dtype, bool staged, void *const
 namespace fdtd {
 int solver_check(fdtd_t h) { return check(h); }
 int solver_device_fail(fdtd_t h, hipError_t e, const char *what) { return device_fail(h, e, what); }
+int step_with_queue(fdtd_t h, long long n, unsigned *queue)
+{
+    int st = check(h);
+    if (st)
+        return st;
+    if (n < 0)
+        return fail(FDTD_E_ARG, "negative step count %lld", n);
+    if (!h->fields_set)
+        return fail(FDTD_E_STATE, "fields were never set");
+    return by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, n, queue); });
+}
 }  // namespace fdtd
 
 namespace {
@@ -784,7 +795,7 @@ int fdtd_step(fdtd_t h, long long n)
         return fail(FDTD_E_STATE, "fields were never set");
     if ((st = use_device(h)))
         return st;
-    return by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, n); });
+    return by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, n, h->sched); });
 }
 
 int fdtd_get_fields(fdtd_t h, void *const host[6], int host_dtype)
@@ -1092,9 +1103,9 @@ int fdtd_autotune(fdtd_t h, int trial_steps, fdtd_schedule *results, int max_res
         apply_schedule(h, &cands[c]);
         const int tb = cands[c].kernel == FDTD_KERNEL_TEMPORAL ? cands[c].tb_steps : 1;
         const long long n = (steps + tb - 1) / tb * tb;  // whole sweeps
-        int st = by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, tb); });
+        int st = by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, tb, h->sched); });
         if (st == FDTD_OK && (e = hipEventRecord(ev0, h->stream)) == hipSuccess) {
-            st = by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, n); });
+            st = by_storage(h->storage, [&](auto tag) { return step_impl<decltype(tag)>(h, n, h->sched); });
             if (st == FDTD_OK)
                 e = hipEventRecord(ev1, h->stream);
             if (st == FDTD_OK && e == hipSuccess)

@@ -93,6 +93,10 @@ hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Field
 // store policy, so the next sweep reads the state from the cache; larger states store
 // non-temporally, which leaves L2 to the halo lines neighbouring tiles share.
 constexpr size_t kStreamCacheBytes = (size_t)256 << 20;
+// 32-bit scheduling counters a queue-scheduled temporal launch uses (zero before the
+// launch, zero again after it): one next-tile index per XCD list, the count of finished
+// workgroups and the mask of lists seen empty.
+constexpr int kSchedWords = 10;
 int temporal_own_rows(int ts, int variant);
 int temporal_width(int variant);
 

@@ -45,4 +45,9 @@ int solver_check(fdtd_t h);
 // Mark the solver failed after a device error and set the message.
 int solver_device_fail(fdtd_t h, hipError_t e, const char *what);
 
+// fdtd_step with the temporal sweeps' scheduling counters (kSchedWords words, zero
+// before and after each launch) taken from queue instead of the solver's arena.
+// Same checks and errors as fdtd_step; the device must be current.
+int step_with_queue(fdtd_t h, long long n, unsigned *queue);
+
 }  // namespace fdtd

@@ -143,6 +143,7 @@ def load_library():
     lib.fdtd_set_fields.argtypes = [vp, p6, i]
     lib.fdtd_set_fields_device.argtypes = [vp, p6, i]
     lib.fdtd_step.argtypes = [vp, ll]
+    lib.fdtd_step_noalloc.argtypes = [vp, ll]
     lib.fdtd_get_fields.argtypes = [vp, p6, i]
     lib.fdtd_get_fields_device.argtypes = [vp, p6, i]
     lib.fdtd_get_coefs.argtypes = [vp, p6, i]
@@ -186,7 +187,8 @@ def load_library():
                  "fdtd_pool_stats", "fdtd_pool_destroy"):
         getattr(lib, name).restype = i
     for name in ("fdtd_opts_default", "fdtd_required_bytes", "fdtd_create", "fdtd_set_fields",
-                 "fdtd_set_fields_device", "fdtd_step", "fdtd_get_fields", "fdtd_get_fields_device",
+                 "fdtd_set_fields_device", "fdtd_step", "fdtd_step_noalloc", "fdtd_get_fields",
+                 "fdtd_get_fields_device",
                  "fdtd_get_coefs", "fdtd_sync", "fdtd_diag", "fdtd_query", "fdtd_destroy"):
         getattr(lib, name).restype = i
     _lib = lib
@@ -364,6 +366,11 @@ class Solver:
     def step(self, n: int = 1) -> None:
         """Enqueue n leapfrog steps (asynchronous)."""
         _check(self._lib.fdtd_step(self._h, int(n)))
+
+    def step_noalloc(self, n: int = 1) -> None:
+        """As step, with no allocation of any kind (scheduling counters in the library's own
+        per-GPU array; calls that overlap on one GPU race)."""
+        _check(self._lib.fdtd_step_noalloc(self._h, int(n)))
 
     def sync(self) -> None:
         _check(self._lib.fdtd_sync(self._h))

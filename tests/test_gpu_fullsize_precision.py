@@ -24,9 +24,9 @@ STEPS = 500
 # stated bounds (rel-L2 vs the FP64 oracle after 500 steps at 512^3, tb = 3; measured
 # 5.6e-6, 2.83e-3, 2.27e-2, 1.25e-5, 9.0e-5)
 BOUND = {"f32": 1e-5, "f16": 5e-3, "bf16": 4e-2, "f16c": 3e-5, "bf16c": 2e-4}
-# max-abs bounds (fields of size ~1): about ten times the largest differences expected from
-# the RMS errors above
-MAXABS = {"f32": 1e-3, "f16": 5e-2, "bf16": 0.5, "f16c": 3e-3, "bf16c": 2e-2}
+# max-abs bounds (fields of size ~1), about 3-6x the measured largest differences
+# (1.58e-5, 9.5e-3, 7.6e-2, 3.6e-5, 3.0e-4: 6.5-7.8x the RMS difference of each run)
+MAXABS = {"f32": 1e-4, "f16": 3e-2, "bf16": 0.3, "f16c": 2e-4, "bf16c": 2e-3}
 
 
 def _P():
@@ -73,7 +73,7 @@ def test_512_precision_vs_oracle():
         assert err < BOUND[storage]
         # no node far outside the bulk of the error: a single wrong node (say off by 0.1) hides
         # in the norm of 8e8 nodes but not here
-        assert mabs < MAXABS[storage] and mabs < 60 * rms
+        assert mabs < MAXABS[storage] and mabs < 20 * rms
 
 
 def test_1024_16bit_vs_fp32():
