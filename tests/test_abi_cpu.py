@@ -101,6 +101,8 @@ def test_invalid_handles_are_rejected():
     assert lib.fdtd_destroy(bogus) == F.E_STATE
     ptrs = (ctypes.c_void_p * 6)()
     assert lib.fdtd_get_fields(None, ptrs, F.F32) == F.E_STATE
+    assert lib.fdtd_step_noalloc(None, 1) == F.E_STATE
+    assert lib.fdtd_step_noalloc(bogus, 1) == F.E_STATE
 
 
 def test_required_bytes():
