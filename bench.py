@@ -134,8 +134,17 @@ def main() -> int:
     q = s.query()
     kernel = q["kernel"]
     steps_per_launch = int(q["steps_per_sweep"])
-    # the bandwidth probe runs before the warm-up steps: it also brings the GPU out of idle
+    # the bandwidth probe and the serving leg run before the warm-up steps: after an idle spell
+    # the GPU's clocks take about 20 ms of stencil load to settle (the first ~10 sweeps run up
+    # to 20 % slow), and the serving leg is such a load, right before the timed region
     probe = copy_probe(stream)
+    serving = None
+    if not args.no_serving:
+        from paper_2504_09118_amd import serve
+
+        serving = serve.bench_point(int(args.serving_budget_gib * 2 ** 30), load=args.serving_load,
+                                    n_requests=args.serving_requests, stream=stream,
+                                    log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     s.step(args.warmup)
     s.sync()
     torch.cuda.synchronize()
@@ -227,17 +236,14 @@ def main() -> int:
         "repetitions": {"n": nrep, "steps_each": chunks, "gcells_mean": round(statistics.fmean(rep_rates), 3),
                         "gcells_std": round(statistics.pstdev(rep_rates), 3),
                         "gcells_min": round(min(rep_rates), 3), "gcells_max": round(max(rep_rates), 3)},
+        "call_ms": [round(x, 4) for x in call_ms] if len(call_ms) <= 32 else None,
         "wall_s": round(wall, 4),
         "energy_check": {"nonfinite": d["nonfinite"], "max_e_tan": d["max_e_tan"]},
     }
 
     result["copy_probe"] = probe
-    if not args.no_serving:
-        from paper_2504_09118_amd import serve
-
-        result["serving"] = serve.bench_point(int(args.serving_budget_gib * 2 ** 30), load=args.serving_load,
-                                              n_requests=args.serving_requests, stream=stream,
-                                              log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    if serving is not None:
+        result["serving"] = serving
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(e, eps, nx, ny, nz, dx, dt, args.cpu_steps, args.cpu_steps_1thread,
                                               args.numpy_steps, gpu_gcells=gcells)
