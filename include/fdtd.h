@@ -330,8 +330,15 @@ int fdtd_destroy(fdtd_t h);
  * (Ce = dt/(dx * mean eps of the edge's four cells)). The forward pass stores
  * (E^n, H^{n-1/2}) every checkpoint_every steps; the backward pass recomputes
  * each segment from its checkpoint (checkpoint-and-recompute), so device
- * memory is ceil(N/K) states + K H-fields (+ the FP64 gradient boxes and,
- * with FP32 storage, their FP32 group sums), not N.
+ * memory is ceil(N/K) states + K H-fields (+ two adjoint states, the FP64
+ * gradient boxes and, with FP32 storage, their FP32 group sums), not N.
+ * Each forward and recompute step is one slab sweep that also adds the source
+ * and (up to 16 probes) records the probes; each reverse step is one fused
+ * sweep (mu' = mu - K(Ce lam), the gradient terms, lam' = lam - L(Ch mu'),
+ * the probe terms) from one adjoint buffer to the other. Environment aids
+ * (none changes the bits): FDTD_ADJ_FUSED = 0 (the one-cell-per-thread
+ * reverse kernels, in place), FDTD_ADJ_VARIANT = 0..3 (tile shape of the
+ * fused sweep; default 1), FDTD_ADJ_ZCHUNKS (its z-split).
  */
 typedef struct fdtd_adjoint *fdtd_adjoint_t;
 
@@ -339,7 +346,7 @@ typedef struct {
     int src_field;            /* E component of the source node (FDTD_EX..FDTD_EZ), or -1 for none */
     int src_i, src_j, src_k;  /* source node, interior (not tangential to a wall) */
     const double *waveform;   /* nsteps values; waveform[n-1] is added after the E update of step n */
-    int nprobes;
+    int nprobes;              /* 0 .. 4096 */
     const int *probes;        /* 4 ints per probe: E component, i, j, k (interior E nodes) */
     long long nsteps;         /* N >= 1 */
     int checkpoint_every;     /* K >= 1 (0: 50) */

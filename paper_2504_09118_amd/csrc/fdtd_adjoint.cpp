@@ -78,7 +78,8 @@ struct fdtd_adjoint {
     long long *d_po;
     double *d_rec, *d_J, *d_grad;
     char *ckpt, *hist;
-    void *adj[6];  // lam Ex Ey Ez, mu Hx Hy Hz (element (0,0,0) of each box)
+    void *adj[2][6];      // two buffers of lam Ex Ey Ez, mu Hx Hy Hz (element (0,0,0) of each box)
+    fdtd::ProbeList pl;   // the probes as sweep arguments (np = 0 when there are more than fit)
     double *gce[3];
     float *gpart[3];  // FP32 group sums of the gCe terms (FP32 storage), else null
     bool forward_done;
@@ -106,6 +107,14 @@ Fields<T> state_of(fdtd_t s)
 }
 
 template <typename T>
+Fields<T> other_of(fdtd_t s)
+{
+    Fields<T> f;
+    for (int q = 0; q < 6; ++q) f.f[q] = (T *)s->fld[1 - s->cur][q];
+    return f;
+}
+
+template <typename T>
 Coefs<T> coefs_of(fdtd_t s)
 {
     Coefs<T> c;
@@ -118,17 +127,42 @@ Coefs<T> coefs_of(fdtd_t s)
     return c;
 }
 
-// One driven step: leapfrog step, point source, probes (rec_row null: none).
+// Point source of step n and the probe list as extras of one slab sweep.
+fdtd::SlabExtras extras_of(const fdtd_adjoint *a, long long n, double *rec_row)
+{
+    fdtd::SlabExtras x{};
+    const long long P = a->s->plan.g.plane;
+    x.sf = a->sf;
+    x.sk = a->sf >= 0 ? (int)(a->so / P) : 0;
+    x.sxy = a->sf >= 0 ? (int)(a->so % P) : 0;
+    x.w = a->sf >= 0 ? a->wave[n] : 0.0;
+    x.pl = a->pl;
+    x.rec_row = rec_row && a->pl.np > 0 ? rec_row : nullptr;
+    return x;
+}
+
+// One driven step: one slab sweep of the solver that also adds the point source to its E node
+// and records the probes (rec_row null: none; with more probes than a sweep carries, a probe
+// kernel records them); J is summed from the records after the forward.
 template <typename T>
 int driven_step(fdtd_adjoint_t a, long long n, double *rec_row)
 {
     fdtd_t s = a->s;
-    if (int st = fdtd_step(s, 1))
-        return st;
-    hipError_t e = fdtd::launch_source_probe<T>(state_of<T>(s), a->sf, a->so, a->sf >= 0 ? a->wave[n] : 0.0,
-                                                rec_row ? a->np : 0, a->d_pf, a->d_po, rec_row, a->d_J, s->stream);
+    const fdtd::SlabExtras x = extras_of(a, n, rec_row);
+    hipError_t e = fdtd::launch_slab_step<T>(s->plan.g, state_of<T>(s), other_of<T>(s), coefs_of<T>(s), s->zchunk,
+                                             s->variant, s->stream, s->nt_stores, &x);
     if (e != hipSuccess)
-        return fdtd::solver_device_fail(s, e, "source/probe kernel");
+        return fdtd::solver_device_fail(s, e, "driven sweep");
+    s->cur = 1 - s->cur;
+    s->steps += 1;
+    s->sweeps += 1;
+    if (rec_row && a->np > 0 && a->pl.np == 0) {
+        // the probe kernel also sums J; here J comes from the records, so it sums into a spare word
+        e = fdtd::launch_source_probe<T>(state_of<T>(s), -1, 0, 0.0, a->np, a->d_pf, a->d_po, rec_row, a->d_J + 1,
+                                         s->stream);
+        if (e != hipSuccess)
+            return fdtd::solver_device_fail(s, e, "probe kernel");
+    }
     return FDTD_OK;
 }
 
@@ -161,6 +195,8 @@ int forward_impl(fdtd_adjoint_t a, double *J)
         if (int st = driven_step<T>(a, n, a->d_rec + (size_t)(n + 1) * a->np))
             return st;
     }
+    if (a->np > 0 && (e = fdtd::launch_probe_objective(a->d_rec, a->N, a->np, a->d_J, s->stream)) != hipSuccess)
+        return fdtd::solver_device_fail(s, e, "probe objective");
     double hJ = 0.0;
     e = hipMemcpyAsync(&hJ, a->d_J, sizeof(double), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess)
@@ -178,11 +214,23 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
     fdtd_t s = a->s;
     const Geom &g = s->plan.g;
     Fields<T> adj;
-    for (int q = 0; q < 6; ++q) adj.f[q] = (T *)a->adj[q];
     const Coefs<T> c = coefs_of<T>(s);
+    // the fused reverse sweep (default) reads one adjoint buffer and writes the other; the plain
+    // form (FDTD_ADJ_FUSED=0: one-cell-per-thread mu and lam kernels plus the probe kernel) works
+    // in place on buffer 0; both give the same bits
+    const char *fe = getenv("FDTD_ADJ_FUSED");
+    const bool fused = !(fe && fe[0] == '0');
+    int cur = 0;
+    auto adj_of = [&](int b) {
+        Fields<T> f;
+        for (int q = 0; q < 6; ++q) f.f[q] = (T *)a->adj[b][q];
+        return f;
+    };
+    adj = adj_of(0);
     hipError_t e = hipSuccess;
-    for (int q = 0; q < 6 && e == hipSuccess; ++q)
-        e = hipMemsetAsync(box_of(a, a->adj[q]), 0, a->fbox, s->stream);
+    for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 6 && e == hipSuccess; ++q)
+            e = hipMemsetAsync(box_of(a, a->adj[b][q]), 0, a->fbox, s->stream);
     for (int q = 0; q < 3 && e == hipSuccess; ++q)
         e = hipMemsetAsync((char *)a->gce[q] - fdtd::kGuardElems * sizeof(double), 0,
                            (size_t)g.box * sizeof(double), s->stream);
@@ -219,10 +267,8 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
                 src.f[3 + f] = q == 0 ? (T *)s->fld[s->cur][3 + f] : slot_h(q - 1, f);
                 dst.f[3 + f] = slot_h(q, f);
             }
-            e = fdtd::launch_slab_step<T>(g, src, dst, c, s->zchunk, s->variant, s->stream, s->nt_stores);
-            if (e == hipSuccess)
-                e = fdtd::launch_source_probe<T>(dst, a->sf, a->so, a->sf >= 0 ? a->wave[n] : 0.0, 0, a->d_pf,
-                                                 a->d_po, nullptr, a->d_J, s->stream);
+            const fdtd::SlabExtras x = extras_of(a, n, nullptr);
+            e = fdtd::launch_slab_step<T>(g, src, dst, c, s->zchunk, s->variant, s->stream, s->nt_stores, &x);
             if (e != hipSuccess)
                 return fdtd::solver_device_fail(s, e, "recompute step");
         }
@@ -230,11 +276,21 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
             const T *h[3];
             for (int f = 0; f < 3; ++f) h[f] = slot_h(n - n0, f);
             // the step n with n % kAdjGroup == 0 closes its group (n = 0 closes the last)
-            e = fdtd::launch_adj_step<T>(g, adj, c, h, a->gce, a->gpart[0] ? a->gpart : nullptr,
-                                         n % fdtd::kAdjGroup == 0, s->stream);
-            if (e == hipSuccess && n >= 1)
-                e = fdtd::launch_adj_probe<T>(adj, a->np, a->d_pf, a->d_po, a->d_rec + (size_t)n * a->np,
-                                              s->stream);
+            if (fused) {
+                const double *rec = n >= 1 ? a->d_rec + (size_t)n * a->np : nullptr;
+                e = fdtd::launch_adj_sweep<T>(g, adj_of(cur), adj_of(1 - cur), c, h, a->gce,
+                                              a->gpart[0] ? a->gpart : nullptr, n % fdtd::kAdjGroup == 0, a->pl,
+                                              rec, s->zchunk, s->stream);
+                cur = 1 - cur;
+                if (e == hipSuccess && rec && a->np > 0 && a->pl.np == 0)
+                    e = fdtd::launch_adj_probe<T>(adj_of(cur), a->np, a->d_pf, a->d_po, rec, s->stream);
+            } else {
+                e = fdtd::launch_adj_step<T>(g, adj, c, h, a->gce, a->gpart[0] ? a->gpart : nullptr,
+                                             n % fdtd::kAdjGroup == 0, s->stream);
+                if (e == hipSuccess && n >= 1)
+                    e = fdtd::launch_adj_probe<T>(adj, a->np, a->d_pf, a->d_po, a->d_rec + (size_t)n * a->np,
+                                                  s->stream);
+            }
             if (e != hipSuccess)
                 return fdtd::solver_device_fail(s, e, "adjoint step");
         }
@@ -251,11 +307,11 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
         fdtd::extents(g, q, X, Y, Z);
         const size_t n = (size_t)X * Y * Z;
         if (lam0_dtype == FDTD_F64) {
-            e = fdtd::launch_unpack<T, double>(g, q, (const T *)a->adj[q], (double *)s->staging, s->stream);
+            e = fdtd::launch_unpack<T, double>(g, q, (const T *)a->adj[cur][q], (double *)s->staging, s->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(lam0[q], s->staging, n * sizeof(double), hipMemcpyDeviceToHost, s->stream);
         } else {
-            e = fdtd::launch_unpack<T, float>(g, q, (const T *)a->adj[q], (float *)s->staging, s->stream);
+            e = fdtd::launch_unpack<T, float>(g, q, (const T *)a->adj[cur][q], (float *)s->staging, s->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(lam0[q], s->staging, n * sizeof(float), hipMemcpyDeviceToHost, s->stream);
         }
@@ -302,6 +358,8 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
     }
     if (p->nprobes < 0 || (p->nprobes > 0 && !p->probes))
         return afail(FDTD_E_ARG, "bad probe list");
+    if (p->nprobes > 4096)
+        return afail(FDTD_E_ARG, "at most 4096 probes (got %d)", p->nprobes);
     for (int q = 0; q < p->nprobes; ++q) {
         const int *pr = p->probes + 4 * q;
         if (!interior_e(s, pr[0], pr[1], pr[2], pr[3]))
@@ -340,7 +398,7 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
     const size_t o_hist = off;
     off += (size_t)K * 3 * a->fbox;
     const size_t o_adj = off;
-    off += 6 * a->fbox;
+    off += 12 * a->fbox;
     const size_t o_gce = off;
     off += 3 * gbox;
     // FP32 storage: the per-step gCe terms are summed in FP32 over groups of kAdjGroup steps
@@ -359,6 +417,7 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
     off += up((size_t)std::max(1, a->np) * sizeof(int));
     const size_t o_po = off;
     off += up((size_t)std::max(1, a->np) * sizeof(long long));
+
     e = hipMalloc((void **)&a->mem, off);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -367,7 +426,8 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
     }
     a->ckpt = a->mem + o_ckpt;
     a->hist = a->mem + o_hist;
-    for (int q = 0; q < 6; ++q) a->adj[q] = a->mem + o_adj + (size_t)q * a->fbox + a->guard;
+    for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 6; ++q) a->adj[b][q] = a->mem + o_adj + (size_t)(6 * b + q) * a->fbox + a->guard;
     for (int q = 0; q < 3; ++q)
         a->gce[q] = (double *)(a->mem + o_gce + (size_t)q * gbox) + fdtd::kGuardElems;
     for (int q = 0; q < 3; ++q)
@@ -377,6 +437,15 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
     a->d_J = (double *)(a->mem + o_j);
     a->d_pf = (int *)(a->mem + o_pf);
     a->d_po = (long long *)(a->mem + o_po);
+    a->pl = fdtd::ProbeList{};
+    if (a->np <= fdtd::kInlineProbes) {
+        a->pl.np = a->np;
+        for (int q = 0; q < a->np; ++q) {
+            a->pl.pf[q] = a->pf[q];
+            a->pl.pk[q] = (int)(a->po[q] / g.plane);
+            a->pl.pxy[q] = (int)(a->po[q] % g.plane);
+        }
+    }
     if (a->np) {
         e = hipMemcpyAsync(a->d_pf, a->pf.data(), a->np * sizeof(int), hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess)

@@ -68,13 +68,33 @@ template <typename T>
 hipError_t launch_fused_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                              const Coefs<T> &c, int zchunk, hipStream_t s);
 
+// Up to kInlineProbes probe nodes carried in a sweep's kernel arguments (probe order kept):
+// component pf, plane pk and in-plane element offset pxy of each.
+constexpr int kInlineProbes = 16;
+struct ProbeList {
+    int np;
+    int pf[kInlineProbes], pk[kInlineProbes], pxy[kInlineProbes];
+};
+
+// Driven-cavity extras a slab sweep can apply (the adjoint's forward and recompute): add w to
+// the E node (component sf, plane sk, in-plane element offset sxy) right after its update
+// (sf < 0: none), then record E of each probe q as a double in rec_row[q] (rec_row null or
+// no probes: none).
+struct SlabExtras {
+    int sf, sk, sxy;
+    double w;
+    ProbeList pl;
+    double *rec_row;
+};
+
 // Slab step (fused sweep with V-wide lanes, prefetch and XCD-aware tiles):
 // reads src, writes dst. variant selects the tile shape (0 = default).
 // nt_stores: store the new state with the non-temporal cache policy (right when
 // the streamed state is larger than the last-level cache; see kStreamCacheBytes).
 template <typename T>
 hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
-                            const Coefs<T> &c, int zchunk, int variant, hipStream_t s, bool nt_stores = true);
+                            const Coefs<T> &c, int zchunk, int variant, hipStream_t s, bool nt_stores = true,
+                            const SlabExtras *extras = nullptr);
 
 // Temporal step: ts (1..3) leapfrog steps in one sweep; reads src, writes dst.
 // Built for FP32, FP16 and BF16 field storage (16-bit fields compute in FP32
@@ -150,6 +170,9 @@ hipError_t launch_init_random(const Geom &g, unsigned long long seed, T *const a
 template <typename T>
 hipError_t launch_source_probe(const Fields<T> &f, int sf, long long so, double w, int np, const int *pf,
                                const long long *po, double *rec_row, double *J, hipStream_t s);
+// J = sum over rows 1..nrows of rec (np values a row) of the row's sum of squares, in probe
+// and row order (the bits of adding one row per step); 1 <= np <= 4096.
+hipError_t launch_probe_objective(const double *rec, long long nrows, int np, double *J, hipStream_t s);
 // lam += 2 rec_row at the probe nodes.
 template <typename T>
 hipError_t launch_adj_probe(const Fields<T> &lam, int np, const int *pf, const long long *po, const double *rec_row,
@@ -161,6 +184,14 @@ constexpr int kAdjGroup = 16;
 template <typename T>
 hipError_t launch_adj_step(const Geom &g, const Fields<T> &a, const Coefs<T> &c, const T *const hist[3],
                            double *const gce[3], float *const gpart[3], bool close_group, hipStream_t s);
+// The fused reverse step (one z-marching sweep): reads a = (lam, mu) from src, writes
+// (lam', mu') to dst; gCe as launch_adj_step; then lam' += 2 rec_row[q] at the probes of pl
+// (rec_row null: none). The bits of launch_adj_step followed by launch_adj_probe. zchunk:
+// z-chunks as the slab sweep.
+template <typename T>
+hipError_t launch_adj_sweep(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c,
+                            const T *const hist[3], double *const gce[3], float *const gpart[3], bool close_group,
+                            const ProbeList &pl, const double *rec_row, int zchunk, hipStream_t s);
 // dJ/d eps per cell (dense x-fastest nx*ny*nz doubles) from dJ/dCe per edge.
 template <typename T>
 hipError_t launch_grad_eps(const Geom &g, const Coefs<T> &c, double *const gce[3], double dx_over_dt, double *out,

@@ -128,7 +128,7 @@ __device__ __forceinline__ void st_plane(T *plane, unsigned plane_bytes, unsigne
 template <typename T, int V, int R, bool CE_ARR, bool CH_ARR, bool NT>
 __global__ void __launch_bounds__(64 * R)
     k_slab(Geom g, Fields<T> src, Fields<T> dst, Coefs<T> c, int kchunk, int ntx, int nty, int ntiles,
-               int xcd_remap)
+               int xcd_remap, SlabExtras xt)
 {
     using vec = typename VecOf<T, V>::type;
     constexpr int TX = 64 * V;       // tile width (cells)
@@ -374,6 +374,39 @@ __global__ void __launch_bounds__(64 * R)
                                                     el<T, V>(hx, v), el<T, V>(hxj, v)));
             }
         }
+        // driven cavity: the point source joins its E node right after the update, then the
+        // probes of this plane read E; the plane tests are uniform, only the owning lane of a node
+        // acts
+        {
+            const int lin = ib + px * j;
+            const bool mine = erow && act && own;
+            if (xt.sf >= 0 && k == xt.sk && mine) {
+                const int d = xt.sxy - lin;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (d != v)
+                        continue;
+                    if (xt.sf == 0)
+                        set_el<T, V>(ex, v, el<T, V>(ex, v) + (T)xt.w);
+                    else if (xt.sf == 1)
+                        set_el<T, V>(ey, v, el<T, V>(ey, v) + (T)xt.w);
+                    else
+                        set_el<T, V>(ez, v, el<T, V>(ez, v) + (T)xt.w);
+                }
+            }
+            if (xt.rec_row) {
+                for (int q = 0; q < xt.pl.np; ++q) {
+                    if (xt.pl.pk[q] != k)
+                        continue;
+                    const int d = xt.pl.pxy[q] - lin;
+                    const int f = xt.pl.pf[q];
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        if (mine && d == v)
+                            xt.rec_row[q] = (double)(f == 0 ? el<T, V>(ex, v) : f == 1 ? el<T, V>(ey, v) : el<T, V>(ez, v));
+                }
+            }
+        }
         {
             const unsigned so = erow && act && own ? off : kDrop;
             st_plane<T, V, NT>(dst.f[0] + pk, plane_bytes, so, ex);
@@ -415,7 +448,7 @@ __global__ void __launch_bounds__(64 * R)
 
 template <typename T, int V, int R, bool NT>
 hipError_t launch_cfg(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c, int zchunk,
-                      hipStream_t s)
+                      hipStream_t s, const SlabExtras &xt)
 {
     constexpr int TX = 64 * V;
     const int kchunk = (g.nz + zchunk - 1) / zchunk;
@@ -427,28 +460,28 @@ hipError_t launch_cfg(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
     if (cea && cha)
         hipLaunchKernelGGL((k_slab<T, V, R, true, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles, xcd_remap());
+                           ntiles, xcd_remap(), xt);
     else if (cea)
         hipLaunchKernelGGL((k_slab<T, V, R, true, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles, xcd_remap());
+                           ntiles, xcd_remap(), xt);
     else if (cha)
         hipLaunchKernelGGL((k_slab<T, V, R, false, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles, xcd_remap());
+                           ntiles, xcd_remap(), xt);
     else
         hipLaunchKernelGGL((k_slab<T, V, R, false, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk, ntx, nty,
-                           ntiles, xcd_remap());
+                           ntiles, xcd_remap(), xt);
     return hipGetLastError();
 }
 
 template <typename T, bool NT>
 hipError_t launch_variant(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c, int zchunk,
-                          int variant, hipStream_t s)
+                          int variant, hipStream_t s, const SlabExtras &xt)
 {
     switch (variant) {
-    case 1: return launch_cfg<T, 2, 8, NT>(g, src, dst, c, zchunk, s);
-    case 2: return launch_cfg<T, 1, 16, NT>(g, src, dst, c, zchunk, s);
-    case 3: return launch_cfg<T, 1, 8, NT>(g, src, dst, c, zchunk, s);
-    default: return launch_cfg<T, 2, 16, NT>(g, src, dst, c, zchunk, s);
+    case 1: return launch_cfg<T, 2, 8, NT>(g, src, dst, c, zchunk, s, xt);
+    case 2: return launch_cfg<T, 1, 16, NT>(g, src, dst, c, zchunk, s, xt);
+    case 3: return launch_cfg<T, 1, 8, NT>(g, src, dst, c, zchunk, s, xt);
+    default: return launch_cfg<T, 2, 16, NT>(g, src, dst, c, zchunk, s, xt);
     }
 }
 
@@ -463,18 +496,22 @@ int slab_width(int variant) { return variant == 2 || variant == 3 ? 64 : 128; }
 
 template <typename T>
 hipError_t launch_slab_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst, const Coefs<T> &c,
-                            int zchunk, int variant, hipStream_t s, bool nt_stores)
+                            int zchunk, int variant, hipStream_t s, bool nt_stores, const SlabExtras *extras)
 {
     zchunk = zchunk < 1 ? 1 : zchunk;
     if (sizeof(T) == 8)
         variant = 3;
-    return nt_stores ? launch_variant<T, true>(g, src, dst, c, zchunk, variant, s)
-                     : launch_variant<T, false>(g, src, dst, c, zchunk, variant, s);
+    SlabExtras none{};
+    none.sf = -1;
+    const SlabExtras &xt = extras ? *extras : none;
+    return nt_stores ? launch_variant<T, true>(g, src, dst, c, zchunk, variant, s, xt)
+                     : launch_variant<T, false>(g, src, dst, c, zchunk, variant, s, xt);
 }
 
 template hipError_t launch_slab_step<float>(const Geom &, const Fields<float> &, const Fields<float> &,
-                                            const Coefs<float> &, int, int, hipStream_t, bool);
+                                            const Coefs<float> &, int, int, hipStream_t, bool, const SlabExtras *);
 template hipError_t launch_slab_step<double>(const Geom &, const Fields<double> &, const Fields<double> &,
-                                             const Coefs<double> &, int, int, hipStream_t, bool);
+                                             const Coefs<double> &, int, int, hipStream_t, bool,
+                                             const SlabExtras *);
 
 }  // namespace fdtd

@@ -208,3 +208,40 @@ def test_duplicate_probes_match_oracle():
     assert abs(J - Jr) <= 1e-12 * Jr
     assert rel(g, gr) <= 1e-10
     assert rel_l2(lam0, lr) <= 1e-10
+
+
+@pytest.mark.parametrize("storage,many", [("f32", False), ("f64", False), ("f32", True)])
+def test_fused_reverse_sweep_equals_the_plain_kernels(monkeypatch, storage, many):
+    """The fused reverse sweep (one z-marching launch per step: mu', gCe, lam' and the probe
+    terms) gives the bits of the one-cell-per-thread kernels (FDTD_ADJ_FUSED=0), on a ragged
+    grid of several tiles and z-chunks, with duplicate probes and a probe on the source node;
+    with more probes than a sweep carries in its arguments (20 > 16) the probe kernels take
+    over and the bits stay the same."""
+    nx, ny, nz, steps = 150, 37, 41, 40
+    eps = ci.uniform_cell_eps(nx, ny, nz, seed=15, lo=1.0, hi=4.0)
+    src = (1, 70, 18, 20)
+    probes = [(1, 70, 18, 20), (2, 3, 35, 1), (0, 149, 1, 40), (2, 3, 35, 1), (1, 10, 0, 5), (0, 64, 20, 21)]
+    if many:
+        probes += [(2,) + p for p in ci.distinct_nodes(77, 14, (1, 1, 0), (nx, ny, nz))]
+    wave = ci.gaussian_pulse(steps, center=12.0, width=5.0)
+    e0 = ci.random_e(nx, ny, nz, seed=16)
+    outs = {}
+    for fused in ("1", "0"):
+        monkeypatch.setenv("FDTD_ADJ_FUSED", fused)
+        outs[fused] = _gradient_box(nx, ny, nz, eps, src, probes, wave, e0, storage, 7)
+    a, b = outs["1"], outs["0"]
+    assert a[0] == b[0]
+    assert np.array_equal(a[1], b[1])
+    for x, y in zip(a[2], b[2]):
+        assert np.array_equal(x, y)
+    assert np.abs(a[1]).max() > 0
+
+
+def _gradient_box(nx, ny, nz, eps, src, probes, wave, e0, storage, k_every):
+    P, A = _pkg()
+    with P.Solver(nx, ny, nz, 1.0, S, eps_r=eps, storage=storage) as s:
+        s.set_fields(e0)
+        with A.Adjoint(s, src, wave, probes, len(wave), checkpoint_every=k_every) as a:
+            J = a.forward()
+            g, lam0 = a.backward(lam0=True)
+    return J, g, lam0
