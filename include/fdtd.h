@@ -328,10 +328,16 @@ int fdtd_destroy(fdtd_t h);
  * n = 16m .. 16m+15, independent of the checkpoint interval), then
  * dJ/d eps_cell = sum over the cell's 12 edges of dJ/dCe * (-Ce^2 dx/dt / 4)
  * (Ce = dt/(dx * mean eps of the edge's four cells)). The forward pass stores
- * (E^n, H^{n-1/2}) every checkpoint_every steps; the backward pass recomputes
- * each segment from its checkpoint (checkpoint-and-recompute), so device
- * memory is ceil(N/K) states + K H-fields (+ two adjoint states, the FP64
- * gradient boxes and, with FP32 storage, their FP32 group sums), not N.
+ * (E^n, H^{n-1/2}) every K = checkpoint_every steps and keeps H^{n+1/2} of
+ * every step of the last segment; the backward pass recomputes each other
+ * segment from its checkpoint (checkpoint-and-recompute), so device memory is
+ * ceil(N/K) states + min(K, N) H-fields (+ two adjoint states, the FP64
+ * gradient boxes and, with FP32 storage, their FP32 group sums). With K >= N
+ * nothing is recomputed: the backward costs one reverse sweep per step.
+ * checkpoint_every = 0 picks K = N when that memory is at most half of the
+ * device's free memory (and within FDTD_HBM_BUDGET bytes when that is set),
+ * else K = ceil(sqrt(2N)), the interval of least memory. Every K gives the
+ * same bits.
  * Each forward and recompute step is one slab sweep that also adds the source
  * and (up to 16 probes) records the probes; each reverse step is one fused
  * sweep (mu' = mu - K(Ce lam), the gradient terms, lam' = lam - L(Ch mu'),
@@ -349,7 +355,7 @@ typedef struct {
     int nprobes;              /* 0 .. 4096 */
     const int *probes;        /* 4 ints per probe: E component, i, j, k (interior E nodes) */
     long long nsteps;         /* N >= 1 */
-    int checkpoint_every;     /* K >= 1 (0: 50) */
+    int checkpoint_every;     /* K >= 1, or 0: automatic (K = N when it fits, see above) */
 } fdtd_adjoint_problem;
 
 /*

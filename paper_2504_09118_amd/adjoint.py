@@ -26,7 +26,7 @@ class Adjoint:
     probes: list of (component, i, j, k).
     """
 
-    def __init__(self, solver: Solver, src, wave, probes, nsteps: int, checkpoint_every: int = 50):
+    def __init__(self, solver: Solver, src, wave, probes, nsteps: int, checkpoint_every: int = 0):
         self._lib = load_library()
         self.solver = solver
         self._h = ctypes.c_void_p(None)
@@ -100,7 +100,7 @@ def _autograd_function():
                 e0 = [np.zeros(sh) for sh in field_shapes(nx, ny, nz)[:3]]
             solver.set_fields(e0, problem.get("h0"))
             adj = Adjoint(solver, problem.get("src"), problem.get("wave"), problem.get("probes", []),
-                          problem["nsteps"], problem.get("checkpoint_every", 50))
+                          problem["nsteps"], problem.get("checkpoint_every", 0))
             try:
                 J = adj.forward()
             except Exception:
@@ -137,7 +137,7 @@ def probe_objective(eps_r, **problem):
 
     problem keys: nsteps, src (component, i, j, k), wave (nsteps values), probes
     (list of (component, i, j, k)); optional dx, dt, e0, h0 (initial state, host
-    arrays; default zero), checkpoint_every (50), storage ("f32" or "f64"), stream.
+    arrays; default zero), checkpoint_every (0: automatic), storage ("f32" or "f64"), stream.
     """
     global _FN
     if _FN is None:

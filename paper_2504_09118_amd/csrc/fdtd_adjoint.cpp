@@ -3,18 +3,21 @@
 //
 // Forward: N single leapfrog steps of the solver, each followed by the point
 // source and the probe reads; the state (E^n, H^{n-1/2}) is copied to a
-// checkpoint every K steps. Backward: for each segment of K steps, last one
-// first, the segment is recomputed from its checkpoint with every H^{n+1/2}
-// written straight into a history slot, then walked in reverse with the
-// adjoint sweeps. Device memory:
-// ceil(N/K) checkpoints of six boxes, K history slots of three H boxes, the
-// adjoint fields (six boxes), FP64 dJ/dCe (three boxes) and the FP64 cell
-// gradient.
+// checkpoint every K steps; the steps of the last segment write each H^{n+1/2}
+// straight into a history slot. Backward: for each segment of K steps, last
+// one first, the segment is recomputed from its checkpoint into the history
+// slots (the last one is already there from the forward), then walked in
+// reverse with the adjoint sweeps. With K >= N there is one segment and no
+// recompute at all. Device memory: ceil(N/K) checkpoints of six boxes,
+// min(K, N) history slots of three H boxes, the adjoint fields (two buffers of
+// six boxes), FP64 dJ/dCe (three boxes) and the FP64 cell gradient.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <unordered_set>
@@ -72,6 +75,8 @@ struct fdtd_adjoint {
     std::vector<long long> po;
     long long N;
     int K, nseg;
+    int nslots;    // history slots: min(K, N)
+    int hist_seg;  // the segment whose H^{n+1/2} the slots hold (-1: none)
     char *mem;
     size_t guard, fbox;
     int *d_pf;
@@ -145,19 +150,36 @@ fdtd::SlabExtras extras_of(const fdtd_adjoint *a, long long n, double *rec_row)
 // and records the probes (rec_row null: none; with more probes than a sweep carries, a probe
 // kernel records them); J is summed from the records after the forward.
 template <typename T>
-int driven_step(fdtd_adjoint_t a, long long n, double *rec_row)
+T *hist_slot(const fdtd_adjoint *a, long long q, int f)
+{
+    return (T *)(a->hist + ((size_t)q * 3 + f) * a->fbox + a->guard);
+}
+
+// One driven step. h_src / h_dst, when not null, replace the solver's H buffers as the
+// step's H input / output (the history slots); E always goes from the solver's current
+// buffer to the other one.
+template <typename T>
+int driven_step(fdtd_adjoint_t a, long long n, double *rec_row, T *const *h_src = nullptr, T *const *h_dst = nullptr)
 {
     fdtd_t s = a->s;
     const fdtd::SlabExtras x = extras_of(a, n, rec_row);
-    hipError_t e = fdtd::launch_slab_step<T>(s->plan.g, state_of<T>(s), other_of<T>(s), coefs_of<T>(s), s->zchunk,
-                                             s->variant, s->stream, s->nt_stores, &x);
+    Fields<T> src = state_of<T>(s), dst = other_of<T>(s);
+    for (int f = 0; f < 3; ++f) {
+        if (h_src)
+            src.f[3 + f] = h_src[f];
+        if (h_dst)
+            dst.f[3 + f] = h_dst[f];
+    }
+    hipError_t e = fdtd::launch_slab_step<T>(s->plan.g, src, dst, coefs_of<T>(s), s->zchunk, s->variant, s->stream,
+                                             s->nt_stores, &x);
     if (e != hipSuccess)
         return fdtd::solver_device_fail(s, e, "driven sweep");
     s->cur = 1 - s->cur;
     s->steps += 1;
     s->sweeps += 1;
     if (rec_row && a->np > 0 && a->pl.np == 0) {
-        // the probe kernel also sums J; here J comes from the records, so it sums into a spare word
+        // the probe kernel reads E only; it also sums J, here into a spare word (J comes from the
+        // records)
         e = fdtd::launch_source_probe<T>(state_of<T>(s), -1, 0, 0.0, a->np, a->d_pf, a->d_po, rec_row, a->d_J + 1,
                                          s->stream);
         if (e != hipSuccess)
@@ -189,12 +211,36 @@ int forward_impl(fdtd_adjoint_t a, double *J)
         e = hipMemsetAsync(a->d_rec, 0, (size_t)(a->N + 1) * a->np * sizeof(double), s->stream);
     if (e != hipSuccess)
         return fdtd::solver_device_fail(s, e, "adjoint forward");
+    // The last segment writes each H^{n+1/2} into its history slot (the backward's recompute
+    // of that segment would write the same bits there); its last step runs a second time with
+    // the solver's buffer as the H output, so the solver ends in state N like any forward.
+    a->hist_seg = -1;
+    const long long nl = (long long)(a->nseg - 1) * a->K;
     for (long long n = 0; n < a->N; ++n) {
         if (n % a->K == 0 && (e = copy_state(a, a->ckpt + (size_t)(n / a->K) * 6 * a->fbox, false)) != hipSuccess)
             return fdtd::solver_device_fail(s, e, "checkpoint");
-        if (int st = driven_step<T>(a, n, a->d_rec + (size_t)(n + 1) * a->np))
+        double *rec = a->d_rec + (size_t)(n + 1) * a->np;
+        if (n < nl) {
+            if (int st = driven_step<T>(a, n, rec))
+                return st;
+            continue;
+        }
+        T *hin[3], *hout[3];
+        for (int f = 0; f < 3; ++f) {
+            hin[f] = n > nl ? hist_slot<T>(a, n - nl - 1, f) : nullptr;
+            hout[f] = hist_slot<T>(a, n - nl, f);
+        }
+        if (int st = driven_step<T>(a, n, rec, n > nl ? hin : nullptr, hout))
             return st;
+        if (n == a->N - 1) {
+            s->cur = 1 - s->cur;  // back to the step's input state
+            s->steps -= 1;
+            s->sweeps -= 1;
+            if (int st = driven_step<T>(a, n, rec, n > nl ? hin : nullptr))
+                return st;
+        }
     }
+    a->hist_seg = a->nseg - 1;
     if (a->np > 0 && (e = fdtd::launch_probe_objective(a->d_rec, a->N, a->np, a->d_J, s->stream)) != hipSuccess)
         return fdtd::solver_device_fail(s, e, "probe objective");
     double hJ = 0.0;
@@ -243,21 +289,19 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
         return fdtd::solver_device_fail(s, e, "adjoint setup");
     // The recompute writes each H^{n+1/2} straight into its history slot: single steps of the
     // slab sweep (the bits of every schedule) with the slot as the H output and the solver's
-    // two E buffers alternating. Cells no sweep writes (wall-normal H, padding) hold the same
-    // values in every state, so the slots take them once, from the first checkpoint.
-    const int nslots = (int)std::min<long long>(a->K, a->N);
-    for (int q = 0; q < nslots && e == hipSuccess; ++q)
-        for (int f = 0; f < 3 && e == hipSuccess; ++f)
-            e = hipMemcpyAsync(a->hist + ((size_t)q * 3 + f) * a->fbox, a->ckpt + (size_t)(3 + f) * a->fbox, a->fbox,
-                               hipMemcpyDeviceToDevice, s->stream);
-    if (e != hipSuccess)
-        return fdtd::solver_device_fail(s, e, "history setup");
-    auto slot_h = [&](long long q, int f) { return (T *)(a->hist + ((size_t)q * 3 + f) * a->fbox + a->guard); };
+    // two E buffers alternating. A sweep writes every H node that any sweep reads (the cells it
+    // leaves alone, past the walls and in the padding, are read by no stencil), so the slots
+    // need no other set-up; they were cleared once at creation, which keeps those cells finite.
+    auto slot_h = [&](long long q, int f) { return hist_slot<T>(a, q, f); };
     for (int seg = a->nseg - 1; seg >= 0; --seg) {
         const long long n0 = (long long)seg * a->K, n1 = std::min(a->N, n0 + a->K);
-        if ((e = copy_state(a, a->ckpt + (size_t)seg * 6 * a->fbox, true)) != hipSuccess)
-            return fdtd::solver_device_fail(s, e, "restore checkpoint");
-        for (long long n = n0; n < n1; ++n) {
+        const bool held = seg == a->hist_seg;  // the forward (or the last recompute) left it there
+        if (!held) {
+            a->hist_seg = -1;
+            if ((e = copy_state(a, a->ckpt + (size_t)seg * 6 * a->fbox, true)) != hipSuccess)
+                return fdtd::solver_device_fail(s, e, "restore checkpoint");
+        }
+        for (long long n = held ? n1 : n0; n < n1; ++n) {
             const long long q = n - n0;
             const int ein = (int)(q & 1) ? 1 - s->cur : s->cur;
             Fields<T> src, dst;
@@ -272,6 +316,7 @@ int backward_impl(fdtd_adjoint_t a, double *grad, void *const lam0[3], int lam0_
             if (e != hipSuccess)
                 return fdtd::solver_device_fail(s, e, "recompute step");
         }
+        a->hist_seg = seg;
         for (long long n = n1 - 1; n >= n0; --n) {
             const T *h[3];
             for (int f = 0; f < 3; ++f) h[f] = slot_h(n - n0, f);
@@ -343,9 +388,8 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
         return afail(FDTD_E_UNSUPPORTED, "the adjoint is built for cubic cells");
     if (p->nsteps < 1)
         return afail(FDTD_E_ARG, "nsteps must be >= 1 (got %lld)", p->nsteps);
-    const int K = p->checkpoint_every ? p->checkpoint_every : 50;
-    if (K < 1)
-        return afail(FDTD_E_ARG, "checkpoint_every must be >= 1 (got %d)", p->checkpoint_every);
+    if (p->checkpoint_every < 0)
+        return afail(FDTD_E_ARG, "checkpoint_every must be >= 0 (got %d)", p->checkpoint_every);
     if (p->src_field >= 0) {
         if (!interior_e(s, p->src_field, p->src_i, p->src_j, p->src_k))
             return afail(FDTD_E_ARG, "source (%d: %d %d %d) is not an interior E node", p->src_field, p->src_i,
@@ -385,10 +429,29 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
         a->po.push_back(g.at(pr[1], pr[2], pr[3]));
     }
     a->N = p->nsteps;
-    a->K = K;
-    a->nseg = (int)((p->nsteps + K - 1) / K);
     a->guard = (size_t)fdtd::kGuardElems * s->plan.fesz;
     a->fbox = s->plan.fbox_bytes;
+    // checkpoints and history for interval k: ceil(N/k) states and min(k, N) H-fields
+    auto stored = [&](long long k) {
+        return (size_t)((a->N + k - 1) / k) * 6 * a->fbox + (size_t)std::min(k, a->N) * 3 * a->fbox;
+    };
+    long long K = p->checkpoint_every;
+    if (K == 0) {
+        // automatic: the whole history (no recompute) when it takes at most half of the free
+        // device memory (and fits FDTD_HBM_BUDGET when set), else the interval that needs the
+        // least memory, about sqrt(2N)
+        size_t fr = 0, tot = 0;
+        double cap = hipMemGetInfo(&fr, &tot) == hipSuccess ? 0.5 * (double)fr : 0.0;
+        const char *budget = getenv("FDTD_HBM_BUDGET");
+        if (budget && *budget)
+            cap = std::min(cap, atof(budget));
+        K = (double)stored(a->N) <= cap ? a->N : std::max(1LL, (long long)std::ceil(std::sqrt(2.0 * (double)a->N)));
+    }
+    K = std::min(K, a->N);
+    a->K = (int)K;
+    a->nseg = (int)((a->N + K - 1) / K);
+    a->nslots = (int)K;
+    a->hist_seg = -1;
     const size_t gbox = ((size_t)g.box * sizeof(double) + 255) / 256 * 256;
     const size_t ncell = (size_t)s->nx * s->ny * s->nz;
     auto up = [](size_t v) { return (v + 255) / 256 * 256; };
@@ -396,7 +459,7 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
     const size_t o_ckpt = off;
     off += (size_t)a->nseg * 6 * a->fbox;
     const size_t o_hist = off;
-    off += (size_t)K * 3 * a->fbox;
+    off += (size_t)a->nslots * 3 * a->fbox;
     const size_t o_adj = off;
     off += 12 * a->fbox;
     const size_t o_gce = off;
@@ -446,7 +509,9 @@ int fdtd_adjoint_create(fdtd_t s, const fdtd_adjoint_problem *p, fdtd_adjoint_t 
             a->pl.pxy[q] = (int)(a->po[q] % g.plane);
         }
     }
-    if (a->np) {
+    // history slots cleared once: the cells no sweep writes stay finite (no stencil reads them)
+    e = hipMemsetAsync(a->hist, 0, (size_t)a->nslots * 3 * a->fbox, s->stream);
+    if (a->np && e == hipSuccess) {
         e = hipMemcpyAsync(a->d_pf, a->pf.data(), a->np * sizeof(int), hipMemcpyHostToDevice, s->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(a->d_po, a->po.data(), a->np * sizeof(long long), hipMemcpyHostToDevice, s->stream);

@@ -4,7 +4,9 @@
   checkpoint segments): dJ/d eps_r and dJ/dE^0 to 1e-10 relative L2.
 - FP32 storage in parity mode (the oracle gets the FP32-rounded coefficients,
   initial state and source values): the FP32 bar of the forward path, 1e-5.
-- Checkpoint-and-recompute is exact: any checkpoint interval gives the same bits.
+- Checkpoint-and-recompute is exact: any checkpoint interval gives the same bits,
+  including the automatic one that keeps the whole history from the forward
+  (no recompute), with a nonzero H^{-1/2} on every node (wall-normal H included).
 - The 128^3, 500-step problem against stored central differences of the FP64
   oracle (16 cells): |g - g_FD| <= 1e-3 max(|g_FD|, 1e-2 max_k |g_FD,k|).
 - torch.autograd: eps_r.grad from J.backward() is the library's gradient, and
@@ -47,24 +49,24 @@ def problem24(nsteps=100):
     return n, eps, src, probes, wave, e0
 
 
-def gpu_gradient(n, eps, src, probes, wave, e0, storage, k_every, lam0=True):
+def gpu_gradient(n, eps, src, probes, wave, e0, storage, k_every, lam0=True, h0=None):
     P, A = _pkg()
     with P.Solver(n, n, n, 1.0, S, eps_r=eps, storage=storage) as s:
-        s.set_fields(e0)
+        s.set_fields(e0, h0)
         with A.Adjoint(s, src, wave, probes, len(wave), checkpoint_every=k_every) as a:
             J = a.forward()
             out = a.backward(lam0=lam0)
     return (J,) + (out if lam0 else (out,))
 
 
-def oracle_gradient(n, eps, src, probes, wave, e0, parity32=False):
+def oracle_gradient(n, eps, src, probes, wave, e0, parity32=False, h0=None):
     ce = oracle.coef_e(n, n, n, 1.0, S, eps)
     ch = oracle.coef_h(n, n, n, 1.0, S)
     if parity32:
         ce, ch = oracle.round_to(ce, np.float32), oracle.round_to(ch, np.float32)
         e0 = [np.asarray(a).astype(np.float32).astype(np.float64) for a in e0]
         wave = np.asarray(wave).astype(np.float32).astype(np.float64)
-    state0 = oracle.make_state(e0)
+    state0 = oracle.make_state(e0, h0)
     res = oadj.adjoint_driven(state0, ce, ch, len(wave), src, wave, probes)
     return res["J"], oadj.grad_eps(res["gce"], eps, 1.0, S), res["lam0"]
 
@@ -94,12 +96,60 @@ def test_adjoint_fp32_parity():
 def test_checkpoint_interval_does_not_change_bits():
     n, eps, src, probes, wave, e0 = problem24(nsteps=60)
     ref = gpu_gradient(n, eps, src, probes, wave, e0, "f32", k_every=60)
-    for k in (1, 7, 25):
+    for k in (0, 1, 7, 25, 1000):
         got = gpu_gradient(n, eps, src, probes, wave, e0, "f32", k_every=k)
         assert got[0] == ref[0]
         assert np.array_equal(got[1], ref[1])
         for a, b in zip(got[2], ref[2]):
             assert np.array_equal(a, b)
+
+
+def test_history_from_the_forward_with_a_nonzero_h0():
+    """H^{-1/2} random on every node, wall-normal H included (which no step changes): the
+    whole history kept from the forward (automatic interval, K = N here) and the
+    recomputed one (K = 7) both match the oracle's adjoint in FP64 and give the same bits
+    in FP32."""
+    n, eps, src, probes, wave, e0 = problem24(nsteps=50)
+    h0 = ci.random_h(n, n, n, seed=8)
+    Jr, gr, lr = oracle_gradient(n, eps, src, probes, wave, e0, h0=h0)
+    for k in (0, 7):
+        J, g, lam0 = gpu_gradient(n, eps, src, probes, wave, e0, "f64", k_every=k, h0=h0)
+        assert abs(J - Jr) <= 1e-12 * Jr
+        assert rel(g, gr) <= 1e-10
+        assert rel_l2(lam0, lr) <= 1e-10
+    a = gpu_gradient(n, eps, src, probes, wave, e0, "f32", k_every=0, h0=h0)
+    b = gpu_gradient(n, eps, src, probes, wave, e0, "f32", k_every=7, h0=h0)
+    assert a[0] == b[0]
+    assert np.array_equal(a[1], b[1])
+    for x, y in zip(a[2], b[2]):
+        assert np.array_equal(x, y)
+
+
+def test_forward_leaves_state_n_and_backward_repeats():
+    """Without a source the forward is N plain steps: the solver ends in the state a second
+    solver reaches with step(N), bit for bit, whichever part of the run wrote the history
+    slots; and two backward passes after one forward give the same bits (the second one
+    recomputes the segment the first one no longer holds)."""
+    P, A = _pkg()
+    n, eps, src, probes, wave, e0 = problem24(nsteps=30)
+    h0 = ci.random_h(n, n, n, seed=9)
+    with P.Solver(n, n, n, 1.0, S, eps_r=eps) as ref:
+        ref.set_fields(e0, h0)
+        ref.step(30)
+        want = ref.get_fields(np.float32)
+    for k in (0, 7, 30):
+        with P.Solver(n, n, n, 1.0, S, eps_r=eps) as s:
+            s.set_fields(e0, h0)
+            with A.Adjoint(s, None, None, probes, 30, checkpoint_every=k) as a:
+                a.forward()
+                for x, y in zip(s.get_fields(np.float32), want):
+                    assert np.array_equal(x.view(np.int32), y.view(np.int32)), k
+                g1, l1 = a.backward(lam0=True)
+                g2, l2 = a.backward(lam0=True)
+        assert np.array_equal(g1, g2)
+        for x, y in zip(l1, l2):
+            assert np.array_equal(x, y)
+        assert np.abs(g1).max() > 0
 
 
 def test_adjoint_argument_errors():
@@ -136,17 +186,22 @@ def test_config_128_gradient_vs_oracle_finite_differences():
     import torch
 
     stream = torch.cuda.Stream()
-    with P.Solver(n, n, n, 1.0, S, eps_r=eps, stream=stream) as s:
-        s.set_fields([np.zeros(sh) for sh in P.field_shapes(n, n, n)[:3]])
-        with A.Adjoint(s, tuple(gold["source"]), wave, probes, steps, checkpoint_every=50) as a:
-            t0 = time.perf_counter()
-            J = a.forward()
-            t1 = time.perf_counter()
-            g = a.backward()
-            t2 = time.perf_counter()
-    print(f"\n128^3 x {steps}: forward {1e3 * (t1 - t0):.1f} ms, backward {1e3 * (t2 - t1):.1f} ms, "
-          f"J = {J:.9e} (oracle {gold['J']:.9e})")
-    assert abs(J - gold["J"]) <= 1e-5 * gold["J"]
+    grads = {}
+    # K = 50: ten segments, nine recomputed; K = 0: the whole history kept from the forward
+    for k_every in (50, 0):
+        with P.Solver(n, n, n, 1.0, S, eps_r=eps, stream=stream) as s:
+            s.set_fields([np.zeros(sh) for sh in P.field_shapes(n, n, n)[:3]])
+            with A.Adjoint(s, tuple(gold["source"]), wave, probes, steps, checkpoint_every=k_every) as a:
+                t0 = time.perf_counter()
+                J = a.forward()
+                t1 = time.perf_counter()
+                g = a.backward()
+                t2 = time.perf_counter()
+        print(f"\n128^3 x {steps}, checkpoint_every {k_every}: forward {1e3 * (t1 - t0):.1f} ms, "
+              f"backward {1e3 * (t2 - t1):.1f} ms, J = {J:.9e} (oracle {gold['J']:.9e})")
+        assert abs(J - gold["J"]) <= 1e-5 * gold["J"]
+        grads[k_every] = g
+    assert np.array_equal(grads[50], grads[0])
     fd = np.array(gold["fd"])
     got = np.array([g[k, j, i] for (i, j, k) in cells])
     floor = 1e-2 * np.abs(fd).max()
