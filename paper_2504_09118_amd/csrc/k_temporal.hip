@@ -22,7 +22,10 @@
 //     (one E buffer per stage, two alternating H buffers), TS + 1 barriers
 //     per plane;
 //   - stage-1 inputs for plane k+1 are prefetched at the top of plane k;
-//     later stages take their inputs from registers of the previous stage;
+//     later stages take their inputs from registers of the previous stage,
+//     updated in place: the registers form rings whose slots are renamed from
+//     plane to plane (the loop is unrolled TS + 2 times), so no value is
+//     copied when it passes from one stage to the next;
 //   - a z-chunk starts TS planes early and ends TS-1 planes late so every
 //     stage sees exact inputs on the planes it stores.
 //   - by default one workgroup per CU takes tile numbers from a counter in
@@ -269,59 +272,64 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     const S *Hx = src.f[3], *Hy = src.f[4], *Hz = src.f[5];
     const vec zero = (vec)(T)0;
 
-    // per-stage registers (index s-1)
-    vec Ecur[TS][3];   // E^{n+s-1}(p_s)
-    vec Hold[TS][3];   // H^{n+s-3/2}(p_s)
-    vec Hprv[TS][2];   // H^{n+s-1/2}(p_s - 1), x and y
-    // With per-node Ch (one more coefficient pipeline in registers) only the last stage keeps
-    // this copy, as Hlast: for a stage s < TS-1 the same values are Hold[s+1] (same plane and
-    // time level), which the E update reads instead.
-    vec Hlast[2];
-    vec Ce[TS][3];     // Ce(p_s)
-    vec Ch[TS][3];     // Ch(p_s)
+    // Per-stage registers live in rings indexed by a compile-time phase ph of the plane loop
+    // (unrolled M times), so that a value moves from stage s to stage s+1 at the next plane by
+    // a change of name, not a register copy; every update is in place.
+    //   E ring roles: -2 (stage-1 E prefetched for plane k+2), -1 (E^n at p_1 + 1),
+    //                 s = 0..TS-1 (E input of stage s at p_s, updated in place to its output);
+    //   H ring roles: -1 (stage-1 H prefetched for plane k+1), s = 0..TS-1 (old H of stage s,
+    //                 updated in place), TS (last stage's new H one plane down);
+    //   coefficient rings: -1 (prefetch), s = 0..TS-1.
+    // Role r of a ring sits in slot (r + off + ph) mod M; the next plane has phase ph - 1, so
+    // role r becomes role r + 1 in place. Stage s's H one plane down, which its E update reads,
+    // is role s+1 of the H ring before stage s+1 updates it.
+    // The kernels with per-node Ch and the compensated types do not unroll (their M copies
+    // spill registers): they run the ring at phase 0 and rotate it by one slot after each
+    // plane, a copy of each live value, as the rename would.
+    constexpr int M = TS + 2;
+    constexpr bool RING = !CH_ARR && !Store<S>::comp;
+    constexpr int U = RING ? M : 1;  // planes per loop iteration
+    vec RE[M][3], RH[M][3], RC[M][3], RK[M][3];
 #pragma unroll
-    for (int s = 0; s < TS; ++s) {
+    for (int r = 0; r < M; ++r) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            Ecur[s][q] = zero;
-            Hold[s][q] = zero;
+            RE[r][q] = zero;
+            RH[r][q] = zero;
             // per-node Ce starts at 0 where the E update has no predicates: a lane outside the
             // domain never loads it, and a zero coefficient makes its E update a no-op
-            Ce[s][q] = NP_E ? zero : (vec)c.ce_s;
-            Ch[s][q] = (vec)c.ch_s;
+            RC[r][q] = NP_E ? zero : (vec)c.ce_s;
+            RK[r][q] = (vec)c.ch_s;
         }
-        Hprv[s][0] = zero;
-        Hprv[s][1] = zero;
     }
-    Hlast[0] = zero;
-    Hlast[1] = zero;
-    vec En1[3] = {zero, zero, zero};  // E^n(p_1 + 1)
+#define ES(r, ph) ((((r) + 2 + (ph)) % M + M) % M)
+#define HS(r, ph) ((((r) + 1 + (ph)) % M + M) % M)
 
     const int k0 = max(0, kb - TS);
     const int kend = ke + TS - 2;  // last loop index
-    // first planes of stage 1
+    // first planes of stage 1, in the phase-0 slots
     if (act) {
         const long long pk = (long long)k0 * P;
-        Ecur[0][0] = ldf(Ex + pk, offs, lp(Ex, pk));
-        Ecur[0][1] = ldf(Ey + pk, offs, lp(Ey, pk));
-        Ecur[0][2] = ldf(Ez + pk, offs, lp(Ez, pk));
+        RE[ES(0, 0)][0] = ldf(Ex + pk, offs, lp(Ex, pk));
+        RE[ES(0, 0)][1] = ldf(Ey + pk, offs, lp(Ey, pk));
+        RE[ES(0, 0)][2] = ldf(Ez + pk, offs, lp(Ez, pk));
         if (k0 + 1 < nz) {
-            En1[0] = ldf(Ex + pk + P, offs, lp(Ex, pk + P));
-            En1[1] = ldf(Ey + pk + P, offs, lp(Ey, pk + P));
-            En1[2] = ldf(Ez + pk + P, offs, lp(Ez, pk + P));
+            RE[ES(-1, 0)][0] = ldf(Ex + pk + P, offs, lp(Ex, pk + P));
+            RE[ES(-1, 0)][1] = ldf(Ey + pk + P, offs, lp(Ey, pk + P));
+            RE[ES(-1, 0)][2] = ldf(Ez + pk + P, offs, lp(Ez, pk + P));
         }
-        Hold[0][0] = ldf(Hx + pk, offs, lp(Hx, pk));
-        Hold[0][1] = ldf(Hy + pk, offs, lp(Hy, pk));
-        Hold[0][2] = ldf(Hz + pk, offs, lp(Hz, pk));
+        RH[HS(0, 0)][0] = ldf(Hx + pk, offs, lp(Hx, pk));
+        RH[HS(0, 0)][1] = ldf(Hy + pk, offs, lp(Hy, pk));
+        RH[HS(0, 0)][2] = ldf(Hz + pk, offs, lp(Hz, pk));
         if (CE_ARR) {
-            Ce[0][0] = ld2(c.ce[0] + pk, offc);
-            Ce[0][1] = ld2(c.ce[1] + pk, offc);
-            Ce[0][2] = ld2(c.ce[2] + pk, offc);
+            RC[HS(0, 0)][0] = ld2(c.ce[0] + pk, offc);
+            RC[HS(0, 0)][1] = ld2(c.ce[1] + pk, offc);
+            RC[HS(0, 0)][2] = ld2(c.ce[2] + pk, offc);
         }
         if (CH_ARR) {
-            Ch[0][0] = ld2(c.ch[0] + pk, offc);
-            Ch[0][1] = ld2(c.ch[1] + pk, offc);
-            Ch[0][2] = ld2(c.ch[2] + pk, offc);
+            RK[HS(0, 0)][0] = ld2(c.ch[0] + pk, offc);
+            RK[HS(0, 0)][1] = ld2(c.ch[1] + pk, offc);
+            RK[HS(0, 0)][2] = ld2(c.ch[2] + pk, offc);
         }
     }
     __syncthreads();  // LDS zeroing done
@@ -332,204 +340,154 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     const unsigned cplane_bytes = (unsigned)(P * (long long)sizeof(T));
     const unsigned lfo = act ? offs : kDrop, lco = act ? offc : kDrop;  // prefetch load offsets
 
-    for (int k = k0; k <= kend; ++k) {
-        // ---------------- prefetch stage-1 inputs of plane k+1 ----------------
-        // (planes past the chunk or the domain, and lanes outside it, read zeros)
-        vec pE[3], pH[3], pCe[3], pCh[3];
-        {
-            const bool pv = k + 1 <= kend && k + 1 < nz;
-            const bool pv2 = pv && k + 2 < nz;
-            const long long pk1 = pv ? (long long)(k + 1) * P : 0;
-            const long long pk2 = pv2 ? pk1 + P : 0;
-            const unsigned n1 = pv ? plane_bytes : 0u, n2 = pv2 ? plane_bytes : 0u, nc = pv ? cplane_bytes : 0u;
-            pE[0] = ldb(Ex + pk2, n2, lfo, lp(Ex, pk2));
-            pE[1] = ldb(Ey + pk2, n2, lfo, lp(Ey, pk2));
-            pE[2] = ldb(Ez + pk2, n2, lfo, lp(Ez, pk2));
-            pH[0] = ldb(Hx + pk1, n1, lfo, lp(Hx, pk1));
-            pH[1] = ldb(Hy + pk1, n1, lfo, lp(Hy, pk1));
-            pH[2] = ldb(Hz + pk1, n1, lfo, lp(Hz, pk1));
+    for (int kk = k0; kk <= kend; kk += U) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                pCe[q] = CE_ARR ? ldb<T>(c.ce[q] + pk1, nc, lco, nullptr) : (vec)c.ce_s;
-                pCh[q] = CH_ARR ? ldb<T>(c.ch[q] + pk1, nc, lco, nullptr) : (vec)c.ch_s;
+        for (int u = 0; u < U; ++u) {
+            const int ph = (M - u) % M;  // a constant once unrolled: 0, M-1, ..., 1
+            const int k = kk + u;
+            if (k > kend)
+                break;
+            // ---------------- prefetch stage-1 inputs of plane k+1 (E of k+2) ----------------
+            // (planes past the chunk or the domain, and lanes outside it, read zeros)
+            {
+                const bool pv = k + 1 <= kend && k + 1 < nz;
+                const bool pv2 = pv && k + 2 < nz;
+                const long long pk1 = pv ? (long long)(k + 1) * P : 0;
+                const long long pk2 = pv2 ? pk1 + P : 0;
+                const unsigned n1 = pv ? plane_bytes : 0u, n2 = pv2 ? plane_bytes : 0u, nc = pv ? cplane_bytes : 0u;
+                RE[ES(-2, ph)][0] = ldb(Ex + pk2, n2, lfo, lp(Ex, pk2));
+                RE[ES(-2, ph)][1] = ldb(Ey + pk2, n2, lfo, lp(Ey, pk2));
+                RE[ES(-2, ph)][2] = ldb(Ez + pk2, n2, lfo, lp(Ez, pk2));
+                RH[HS(-1, ph)][0] = ldb(Hx + pk1, n1, lfo, lp(Hx, pk1));
+                RH[HS(-1, ph)][1] = ldb(Hy + pk1, n1, lfo, lp(Hy, pk1));
+                RH[HS(-1, ph)][2] = ldb(Hz + pk1, n1, lfo, lp(Hz, pk1));
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    if (CE_ARR)
+                        RC[HS(-1, ph)][q] = ldb<T>(c.ce[q] + pk1, nc, lco, nullptr);
+                    if (CH_ARR)
+                        RK[HS(-1, ph)][q] = ldb<T>(c.ch[q] + pk1, nc, lco, nullptr);
+                }
             }
-        }
-        // ---------------- stage the E input of every stage ----------------
-        if (lane_ok) {
+            // ---------------- stage the E input of every stage ----------------
+            if (lane_ok) {
 #pragma unroll
-            for (int s = 0; s < TS; ++s)
+                for (int s = 0; s < TS; ++s)
 #pragma unroll
-                for (int q = 0; q < 3; ++q) *(vec *)&sE[s][q][lr][lc] = Ecur[s][q];
-        }
-        __syncthreads();
+                    for (int q = 0; q < 3; ++q) *(vec *)&sE[s][q][lr][lc] = RE[ES(s, ph)][q];
+            }
+            __syncthreads();
 
-        vec hout[TS][3];
-        vec eout[TS][3];
 #pragma unroll
-        for (int s = 0; s < TS; ++s) {
-            const int p = k - s;  // plane of stage s+1
-            const int lo = max(0, kb - TS + s), hi = min(nz - 1, ke + TS - 2 - s);
-            const bool live = p >= lo && p <= hi;
-            // ---- E update of the previous stage (its H was staged in the previous phase) ----
-            if (s > 0) {
-                const int sp = s - 1;
-                const int pp = k - sp;
-                const int lop = max(0, kb - TS + sp), hip = min(nz - 1, ke + TS - 2 - sp);
-                const bool livep = pp >= lop && pp <= hip;
-                const int hb = (sp + 1) & 1;
-                vec ex = Ecur[sp][0], ey = Ecur[sp][1], ez = Ecur[sp][2];
-                if (livep && (NP_E || act)) {
-                    const vec hzj = *(const vec *)&sH[hb][2][lr - 1][lc];  // Hz(i, j-1)
-                    const vec hxj = *(const vec *)&sH[hb][0][lr - 1][lc];  // Hx(i, j-1)
-                    const T hzl = sH[hb][2][lr][lc - 1];                   // Hz(ib-1, j)
-                    const T hyl = sH[hb][1][lr][lc - 1];                   // Hy(ib-1, j)
+            for (int s = 0; s <= TS; ++s) {
+                // ---- E update of stage s-1 (its H was staged in the previous phase) ----
+                if (s > 0) {
+                    const int sp = s - 1;
+                    const int pp = k - sp;
+                    const int lop = sp == TS - 1 ? max(0, kb - 1) : max(0, kb - TS + sp);
+                    const int hip = sp == TS - 1 ? ke - 1 : min(nz - 1, ke + TS - 2 - sp);
+                    const bool livep = pp >= lop && pp <= hip;
+                    const int hb = (sp + 1) & 1;
+                    vec *E = RE[ES(sp, ph)];
+                    const vec *Hn = RH[HS(sp, ph)];      // H^{n+sp+1/2}(p_sp), just updated
+                    const vec *Hd = RH[HS(sp + 1, ph)];  // the same H one plane down
+                    const vec *Cs = RC[HS(sp, ph)];
+                    if (livep && (NP_E || act)) {
+                        const vec hzj = *(const vec *)&sH[hb][2][lr - 1][lc];  // Hz(i, j-1)
+                        const vec hxj = *(const vec *)&sH[hb][0][lr - 1][lc];  // Hx(i, j-1)
+                        const T hzl = sH[hb][2][lr][lc - 1];                   // Hz(ib-1, j)
+                        const T hyl = sH[hb][1][lr][lc - 1];                   // Hy(ib-1, j)
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            const int i = ib + v;
+                            if (!NP_E && i >= nx)
+                                continue;
+                            const T hz_im = v > 0 ? Hn[2][v - 1] : hzl;
+                            const T hy_im = v > 0 ? Hn[1][v - 1] : hyl;
+                            if (NP_E || (j >= 1 && pp >= 1))
+                                E[0][v] = curl_update(E[0][v], Cs[0][v], Hn[2][v], hzj[v], Hn[1][v], Hd[1][v]);
+                            if (NP_E || (i >= 1 && pp >= 1))
+                                E[1][v] = curl_update(E[1][v], Cs[1][v], Hn[0][v], Hd[0][v], Hn[2][v], hz_im);
+                            if (NP_E || (i >= 1 && j >= 1))
+                                E[2][v] = curl_update(E[2][v], Cs[2][v], Hn[1][v], hy_im, Hn[0][v], hxj[v]);
+                        }
+                    }
+                    if (sp < TS - 1 && !livep) {
+                        E[0] = zero;
+                        E[1] = zero;
+                        E[2] = zero;
+                    }
+                    if (sp == TS - 1) {
+                        // unconditional stores (see st_plane); the cell at i = nx of a lane whose
+                        // second cell leaves the domain carries its loaded, never-updated value (a
+                        // wall or padding constant equal in both buffers), so storing both cells
+                        // is exact
+                        const bool wr = livep && own && pp >= kb;
+                        const unsigned so = wr ? offs : kDrop;
+                        const long long pk = (long long)(pp > 0 ? pp : 0) * P;
+                        st_plane<S, NT>(dst.f[0] + pk, plane_bytes, so, lq(dst.f[0], pk), E[0]);
+                        st_plane<S, NT>(dst.f[1] + pk, plane_bytes, so, lq(dst.f[1], pk), E[1]);
+                        st_plane<S, NT>(dst.f[2] + pk, plane_bytes, so, lq(dst.f[2], pk), E[2]);
+                        st_plane<S, NT>(dst.f[3] + pk, plane_bytes, so, lq(dst.f[3], pk), Hn[0]);
+                        st_plane<S, NT>(dst.f[4] + pk, plane_bytes, so, lq(dst.f[4], pk), Hn[1]);
+                        st_plane<S, NT>(dst.f[5] + pk, plane_bytes, so, lq(dst.f[5], pk), Hn[2]);
+                    }
+                }
+                if (s == TS)
+                    break;
+                // ---- H update of stage s, in place ----
+                const int p = k - s;  // plane of stage s+1
+                const int lo = max(0, kb - TS + s), hi = min(nz - 1, ke + TS - 2 - s);
+                const bool live = p >= lo && p <= hi;
+                const vec *en = RE[ES(s - 1, ph)];  // E input at plane p+1 (own column): role -1 or stage s-1's output
+                const vec *Es = RE[ES(s, ph)];
+                const vec *Ks = RK[HS(s, ph)];
+                vec *H = RH[HS(s, ph)];
+                const int hb = (s + 1) & 1;
+                if (live && (NP_H || act)) {
+                    const vec ezj = *(const vec *)&sE[s][2][lr + 1][lc];  // Ez(i, j+1)
+                    const vec exj = *(const vec *)&sE[s][0][lr + 1][lc];  // Ex(i, j+1)
+                    const T ezr = sE[s][2][lr][lc + V];                    // Ez(ib+V, j)
+                    const T eyr = sE[s][1][lr][lc + V];                    // Ey(ib+V, j)
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
                         const int i = ib + v;
-                        if (!NP_E && i >= nx)
+                        if (!NP_H && i >= nx)
                             continue;
-                        const T hz_im = v > 0 ? hout[sp][2][v - 1] : hzl;
-                        const T hy_im = v > 0 ? hout[sp][1][v - 1] : hyl;
-                        if (NP_E || (j >= 1 && pp >= 1))
-                            ex[v] = curl_update(Ecur[sp][0][v], Ce[sp][0][v], hout[sp][2][v], hzj[v], hout[sp][1][v],
-                                                CH_ARR ? Hold[sp + 1][1][v] : Hprv[sp][1][v]);
-                        if (NP_E || (i >= 1 && pp >= 1))
-                            ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], CH_ARR ? Hold[sp + 1][0][v] : Hprv[sp][0][v],
-                                                hout[sp][2][v], hz_im);
-                        if (NP_E || (i >= 1 && j >= 1))
-                            ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
-                                                hxj[v]);
+                        const T ez_ip = v + 1 < V ? Es[2][v + 1] : ezr;
+                        const T ey_ip = v + 1 < V ? Es[1][v + 1] : eyr;
+                        if (NP_H || i >= 1)
+                            H[0][v] = curl_update(H[0][v], Ks[0][v], en[1][v], Es[1][v], ezj[v], Es[2][v]);
+                        if (NP_H || j >= 1)
+                            H[1][v] = curl_update(H[1][v], Ks[1][v], ez_ip, Es[2][v], en[0][v], Es[0][v]);
+                        if (NP_H || p >= 1)
+                            H[2][v] = curl_update(H[2][v], Ks[2][v], exj[v], Es[0][v], ey_ip, Es[1][v]);
                     }
                 }
-                if (!livep) {
-                    ex = zero;
-                    ey = zero;
-                    ez = zero;
+                if (lane_ok) {
+                    *(vec *)&sH[hb][0][lr][lc] = H[0];
+                    *(vec *)&sH[hb][1][lr][lc] = H[1];
+                    *(vec *)&sH[hb][2][lr][lc] = H[2];
                 }
-                eout[sp][0] = ex;
-                eout[sp][1] = ey;
-                eout[sp][2] = ez;
+                __syncthreads();
             }
-            // ---- H update of stage s ----
-            const vec *en = s == 0 ? En1 : eout[s - 1];  // E input at plane p+1 (own column)
-            const int hb = (s + 1) & 1;
-            vec hx = Hold[s][0], hy = Hold[s][1], hz = Hold[s][2];
-            if (live && (NP_H || act)) {
-                const vec ezj = *(const vec *)&sE[s][2][lr + 1][lc];  // Ez(i, j+1)
-                const vec exj = *(const vec *)&sE[s][0][lr + 1][lc];  // Ex(i, j+1)
-                const T ezr = sE[s][2][lr][lc + V];                    // Ez(ib+V, j)
-                const T eyr = sE[s][1][lr][lc + V];                    // Ey(ib+V, j)
+            if (!RING) {
+                // role r moves to role r + 1: every ring shifts one slot up (the values that
+                // wrap round are dead: the next prefetch overwrites them)
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const int i = ib + v;
-                    if (!NP_H && i >= nx)
-                        continue;
-                    const T ez_ip = v + 1 < V ? Ecur[s][2][v + 1] : ezr;
-                    const T ey_ip = v + 1 < V ? Ecur[s][1][v + 1] : eyr;
-                    if (NP_H || i >= 1)
-                        hx[v] = curl_update(Hold[s][0][v], Ch[s][0][v], en[1][v], Ecur[s][1][v], ezj[v],
-                                            Ecur[s][2][v]);
-                    if (NP_H || j >= 1)
-                        hy[v] = curl_update(Hold[s][1][v], Ch[s][1][v], ez_ip, Ecur[s][2][v], en[0][v],
-                                            Ecur[s][0][v]);
-                    if (NP_H || p >= 1)
-                        hz[v] = curl_update(Hold[s][2][v], Ch[s][2][v], exj[v], Ecur[s][0][v], ey_ip,
-                                            Ecur[s][1][v]);
-                }
-            }
-            hout[s][0] = hx;
-            hout[s][1] = hy;
-            hout[s][2] = hz;
-            if (lane_ok) {
-                *(vec *)&sH[hb][0][lr][lc] = hx;
-                *(vec *)&sH[hb][1][lr][lc] = hy;
-                *(vec *)&sH[hb][2][lr][lc] = hz;
-            }
-            __syncthreads();
-        }
-        // ---------------- E update of the last stage and the stores ----------------
-        {
-            constexpr int sp = TS - 1;
-            const int pp = k - sp;
-            const int lop = max(0, kb - 1), hip = ke - 1;
-            const bool livep = pp >= lop && pp <= hip;
-            const int hb = (sp + 1) & 1;
-            vec ex = Ecur[sp][0], ey = Ecur[sp][1], ez = Ecur[sp][2];
-            if (livep && (NP_E || act)) {
-                const vec hzj = *(const vec *)&sH[hb][2][lr - 1][lc];
-                const vec hxj = *(const vec *)&sH[hb][0][lr - 1][lc];
-                const T hzl = sH[hb][2][lr][lc - 1];
-                const T hyl = sH[hb][1][lr][lc - 1];
+                for (int r = M - 1; r > 0; --r)
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const int i = ib + v;
-                    if (!NP_E && i >= nx)
-                        continue;
-                    const T hz_im = v > 0 ? hout[sp][2][v - 1] : hzl;
-                    const T hy_im = v > 0 ? hout[sp][1][v - 1] : hyl;
-                    if (NP_E || (j >= 1 && pp >= 1))
-                        ex[v] = curl_update(Ecur[sp][0][v], Ce[sp][0][v], hout[sp][2][v], hzj[v], hout[sp][1][v],
-                                            CH_ARR ? Hlast[1][v] : Hprv[sp][1][v]);
-                    if (NP_E || (i >= 1 && pp >= 1))
-                        ey[v] = curl_update(Ecur[sp][1][v], Ce[sp][1][v], hout[sp][0][v], CH_ARR ? Hlast[0][v] : Hprv[sp][0][v],
-                                            hout[sp][2][v], hz_im);
-                    if (NP_E || (i >= 1 && j >= 1))
-                        ez[v] = curl_update(Ecur[sp][2][v], Ce[sp][2][v], hout[sp][1][v], hy_im, hout[sp][0][v],
-                                            hxj[v]);
-                }
+                    for (int q = 0; q < 3; ++q) {
+                        RE[r][q] = RE[r - 1][q];
+                        RH[r][q] = RH[r - 1][q];
+                        RC[r][q] = RC[r - 1][q];
+                        RK[r][q] = RK[r - 1][q];
+                    }
             }
-            {
-                // unconditional stores (see st_plane); the cell at i = nx of a lane whose second
-                // cell leaves the domain carries its loaded, never-updated value (a wall or
-                // padding constant equal in both buffers), so storing both cells is exact
-                const bool wr = livep && own && pp >= kb;
-                const unsigned so = wr ? offs : kDrop;
-                const long long pk = (long long)(pp > 0 ? pp : 0) * P;
-                st_plane<S, NT>(dst.f[0] + pk, plane_bytes, so, lq(dst.f[0], pk), ex);
-                st_plane<S, NT>(dst.f[1] + pk, plane_bytes, so, lq(dst.f[1], pk), ey);
-                st_plane<S, NT>(dst.f[2] + pk, plane_bytes, so, lq(dst.f[2], pk), ez);
-                st_plane<S, NT>(dst.f[3] + pk, plane_bytes, so, lq(dst.f[3], pk), hout[sp][0]);
-                st_plane<S, NT>(dst.f[4] + pk, plane_bytes, so, lq(dst.f[4], pk), hout[sp][1]);
-                st_plane<S, NT>(dst.f[5] + pk, plane_bytes, so, lq(dst.f[5], pk), hout[sp][2]);
-            }
-            eout[sp][0] = ex;
-            eout[sp][1] = ey;
-            eout[sp][2] = ez;
-        }
-        if (CH_ARR) {
-            Hlast[0] = hout[TS - 1][0];
-            Hlast[1] = hout[TS - 1][1];
-        }
-        // ---------------- rotate: stage s feeds stage s+1 at the next plane ----------------
-#pragma unroll
-        for (int s = TS - 1; s >= 0; --s) {
-            if (!CH_ARR) {
-                Hprv[s][0] = hout[s][0];
-                Hprv[s][1] = hout[s][1];
-            }
-            if (s + 1 < TS) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    Ecur[s + 1][q] = eout[s][q];
-                    Hold[s + 1][q] = hout[s][q];
-                    if (CE_ARR)
-                        Ce[s + 1][q] = Ce[s][q];
-                    if (CH_ARR)
-                        Ch[s + 1][q] = Ch[s][q];
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            Ecur[0][q] = En1[q];
-            En1[q] = pE[q];
-            Hold[0][q] = pH[q];
-            if (CE_ARR)
-                Ce[0][q] = pCe[q];
-            if (CH_ARR)
-                Ch[0][q] = pCh[q];
         }
     }
+#undef ES
+#undef HS
 }
 
 // Tile number of virtual block v (with one workgroup per tile, v is the
@@ -846,12 +804,16 @@ template hipError_t launch_temporal_step<float>(const Geom &, const Fields<float
                                                 const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
 template hipError_t launch_temporal_step<f16>(const Geom &, const Fields<f16> &, const Fields<f16> &,
                                               const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
+
 template hipError_t launch_temporal_step<bf16>(const Geom &, const Fields<bf16> &, const Fields<bf16> &,
                                                const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
+
 template hipError_t launch_temporal_step<f16c>(const Geom &, const Fields<f16c> &, const Fields<f16c> &,
                                                const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
+
 template hipError_t launch_temporal_step<bf16c>(const Geom &, const Fields<bf16c> &, const Fields<bf16c> &,
                                                 const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
+
 
 }  // namespace fdtd
 
