@@ -21,8 +21,11 @@ eigenvalue set of the one-step map on a small cavity, exact PEC walls, div H
 and div D invariance, exact conservation of the discrete energy, cyclic axis
 equivariance, linearity and agreement of the two implementations.
 
-Parity unpinned (conventions the paper does not fix, tested for
-self-consistency only): the four-cell / two-cell coefficient averaging rule.
+The four-cell / two-cell coefficient averaging rule is a convention the paper
+does not fix (its materials are scalars); its evaluation here is pinned by
+single inclusions whose changed edges and faces, and their values, are
+counted by hand. Parity unpinned: the random-input conventions of
+cavity_inputs (distributions the paper does not state).
 """
 
 from __future__ import annotations
