@@ -91,8 +91,10 @@ __device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *
         typename V2<C>::type r;
         if constexpr (Store<S>::comp) {
             const unsigned short q = *(FDTD_GLOBAL const unsigned short *)(uni(lo_plane) + boff / 2);
-            r[0] = Store<S>::dec(a, (signed char)(q & 0xff));
-            r[1] = Store<S>::dec(b, (signed char)(q >> 8));
+            float x0, x1;
+            Store<S>::dec2(u, q, x0, x1);
+            r[0] = x0;
+            r[1] = x1;
         } else {
             r[0] = Store<S>::widen(a);
             r[1] = Store<S>::widen(b);
@@ -149,7 +151,9 @@ __device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigne
 // buffer's range: an offset at or past nrec (kDrop for a lane outside the domain, or nrec = 0
 // for a plane past the chunk) reads zeros. The prefetch loads every plane this way, so it
 // needs neither a branch nor registers cleared ahead of the loads.
-template <typename S>
+typedef unsigned RawPair __attribute__((ext_vector_type(2)));
+
+template <typename S, bool RAW = false>
 __device__ __forceinline__ typename V2<typename Store<S>::C>::type ldb(const S *plane, unsigned nrec, unsigned boff,
                                                                        const char *lo_plane)
 {
@@ -167,8 +171,20 @@ __device__ __forceinline__ typename V2<typename Store<S>::C>::type ldb(const S *
             const __amdgpu_buffer_rsrc_t rq =
                 __builtin_amdgcn_make_buffer_rsrc((void *)lo_plane, 0, (int)(nrec / 2), kRawBufferWord3);
             const unsigned short q = __builtin_amdgcn_raw_buffer_load_b16(rq, boff / 2, 0, 0);
-            out[0] = Store<S>::dec(a, (signed char)(q & 0xff));
-            out[1] = Store<S>::dec(b, (signed char)(q >> 8));
+            if constexpr (RAW) {
+                // the loaded bits as they are (decoded where they are first used, see dec_raw),
+                // carried as one 64-bit vector: a residual put into a float element on its own
+                // would be a denormal bit pattern, which the compiler may flush
+                RawPair raw;
+                raw.x = u;
+                raw.y = q;
+                return __builtin_bit_cast(typename V2<C>::type, raw);
+            } else {
+                float x0, x1;
+                Store<S>::dec2(u, q, x0, x1);
+                out[0] = x0;
+                out[1] = x1;
+            }
         } else {
             out[0] = Store<S>::widen(a);
             out[1] = Store<S>::widen(b);
@@ -182,6 +198,21 @@ __device__ __forceinline__ typename V2<typename Store<S>::C>::type ldb(const S *
         (void)lo_plane;
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
         return __builtin_bit_cast(typename V2<C>::type, __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0));
+    }
+}
+
+// Decodes, in place, two compensated cells loaded by ldb<S, true> (no-op for other types):
+// the decode waits for the load, so it runs where the values are first needed, a plane
+// after the prefetch, not where the load is issued.
+template <typename S>
+__device__ __forceinline__ void dec_raw(typename V2<typename Store<S>::C>::type &v)
+{
+    if constexpr (Store<S>::comp) {
+        const RawPair raw = __builtin_bit_cast(RawPair, v);
+        float x0, x1;
+        Store<S>::dec2(raw.x, raw.y, x0, x1);
+        v[0] = x0;
+        v[1] = x1;
     }
 }
 
@@ -307,20 +338,22 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
 
     const int k0 = max(0, kb - TS);
     const int kend = ke + TS - 2;  // last loop index
+    const unsigned plane_bytes = (unsigned)(P * (long long)sizeof(S));
+    const unsigned cplane_bytes = (unsigned)(P * (long long)sizeof(T));
     // first planes of stage 1, in the phase-0 slots
     if (act) {
         const long long pk = (long long)k0 * P;
         RE[ES(0, 0)][0] = ldf(Ex + pk, offs, lp(Ex, pk));
         RE[ES(0, 0)][1] = ldf(Ey + pk, offs, lp(Ey, pk));
         RE[ES(0, 0)][2] = ldf(Ez + pk, offs, lp(Ez, pk));
-        if (k0 + 1 < nz) {
-            RE[ES(-1, 0)][0] = ldf(Ex + pk + P, offs, lp(Ex, pk + P));
-            RE[ES(-1, 0)][1] = ldf(Ey + pk + P, offs, lp(Ey, pk + P));
-            RE[ES(-1, 0)][2] = ldf(Ez + pk + P, offs, lp(Ez, pk + P));
-        }
-        RH[HS(0, 0)][0] = ldf(Hx + pk, offs, lp(Hx, pk));
-        RH[HS(0, 0)][1] = ldf(Hy + pk, offs, lp(Hy, pk));
-        RH[HS(0, 0)][2] = ldf(Hz + pk, offs, lp(Hz, pk));
+        // E(k0+1) and H(k0) as loaded bits: the first plane decodes them like every prefetch
+        const unsigned n1 = k0 + 1 < nz ? plane_bytes : 0u;
+        RE[ES(-1, 0)][0] = ldb<S, true>(Ex + pk + P, n1, offs, lp(Ex, pk + P));
+        RE[ES(-1, 0)][1] = ldb<S, true>(Ey + pk + P, n1, offs, lp(Ey, pk + P));
+        RE[ES(-1, 0)][2] = ldb<S, true>(Ez + pk + P, n1, offs, lp(Ez, pk + P));
+        RH[HS(0, 0)][0] = ldb<S, true>(Hx + pk, plane_bytes, offs, lp(Hx, pk));
+        RH[HS(0, 0)][1] = ldb<S, true>(Hy + pk, plane_bytes, offs, lp(Hy, pk));
+        RH[HS(0, 0)][2] = ldb<S, true>(Hz + pk, plane_bytes, offs, lp(Hz, pk));
         if (CE_ARR) {
             RC[HS(0, 0)][0] = ld2(c.ce[0] + pk, offc);
             RC[HS(0, 0)][1] = ld2(c.ce[1] + pk, offc);
@@ -336,8 +369,6 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     // vmcnt(0): the prologue loads land in registers the loop carries; without this wait the
     // compiler's conservative merge at the loop head makes every plane wait for its own prefetch
     __builtin_amdgcn_s_waitcnt(0x0F70);
-    const unsigned plane_bytes = (unsigned)(P * (long long)sizeof(S));
-    const unsigned cplane_bytes = (unsigned)(P * (long long)sizeof(T));
     const unsigned lfo = act ? offs : kDrop, lco = act ? offc : kDrop;  // prefetch load offsets
 
     for (int kk = k0; kk <= kend; kk += U) {
@@ -347,6 +378,13 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
             const int k = kk + u;
             if (k > kend)
                 break;
+            // residual planes: their bases are formed per plane from the field bases (a
+            // loop-invariant copy per field would hold 24 more SGPRs)
+            long long lo = g.lo_off;
+            if constexpr (Store<S>::comp)
+                __asm__ volatile("" : "+s"(lo));
+            auto lp = [&](const S *base, long long pk) { return (const char *)base + lo + pk; };
+            auto lq = [&](S *base, long long pk) { return (char *)base + lo + pk; };
             // ---------------- prefetch stage-1 inputs of plane k+1 (E of k+2) ----------------
             // (planes past the chunk or the domain, and lanes outside it, read zeros)
             {
@@ -355,12 +393,12 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                 const long long pk1 = pv ? (long long)(k + 1) * P : 0;
                 const long long pk2 = pv2 ? pk1 + P : 0;
                 const unsigned n1 = pv ? plane_bytes : 0u, n2 = pv2 ? plane_bytes : 0u, nc = pv ? cplane_bytes : 0u;
-                RE[ES(-2, ph)][0] = ldb(Ex + pk2, n2, lfo, lp(Ex, pk2));
-                RE[ES(-2, ph)][1] = ldb(Ey + pk2, n2, lfo, lp(Ey, pk2));
-                RE[ES(-2, ph)][2] = ldb(Ez + pk2, n2, lfo, lp(Ez, pk2));
-                RH[HS(-1, ph)][0] = ldb(Hx + pk1, n1, lfo, lp(Hx, pk1));
-                RH[HS(-1, ph)][1] = ldb(Hy + pk1, n1, lfo, lp(Hy, pk1));
-                RH[HS(-1, ph)][2] = ldb(Hz + pk1, n1, lfo, lp(Hz, pk1));
+                RE[ES(-2, ph)][0] = ldb<S, true>(Ex + pk2, n2, lfo, lp(Ex, pk2));
+                RE[ES(-2, ph)][1] = ldb<S, true>(Ey + pk2, n2, lfo, lp(Ey, pk2));
+                RE[ES(-2, ph)][2] = ldb<S, true>(Ez + pk2, n2, lfo, lp(Ez, pk2));
+                RH[HS(-1, ph)][0] = ldb<S, true>(Hx + pk1, n1, lfo, lp(Hx, pk1));
+                RH[HS(-1, ph)][1] = ldb<S, true>(Hy + pk1, n1, lfo, lp(Hy, pk1));
+                RH[HS(-1, ph)][2] = ldb<S, true>(Hz + pk1, n1, lfo, lp(Hz, pk1));
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     if (CE_ARR)
@@ -368,6 +406,12 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                     if (CH_ARR)
                         RK[HS(-1, ph)][q] = ldb<T>(c.ch[q] + pk1, nc, lco, nullptr);
                 }
+            }
+            // compensated types: the previous plane's prefetch, decoded now (E role -1, H role 0)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                dec_raw<S>(RE[ES(-1, ph)][q]);
+                dec_raw<S>(RH[HS(0, ph)][q]);
             }
             // ---------------- stage the E input of every stage ----------------
             if (lane_ok) {
@@ -738,6 +782,7 @@ void temporal_tiling(const Geom &g, int ts, int zchunk, int *kchunk, int *ntx, i
     *ntiles = *ntx * *nty * nzc;
 }
 
+
 hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, int ts, bool ce_arr, bool ch_arr,
                                  hipStream_t s, unsigned *queue)
 {
@@ -785,6 +830,7 @@ hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, 
     return hipGetLastError();
 }
 
+
 template <typename T>
 hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
                                 const Coefs<typename Store<T>::C> &c, int zchunk, int ts, int variant,
@@ -800,13 +846,22 @@ hipError_t launch_temporal_step(const Geom &g, const Fields<T> &src, const Field
     return launch_shape<T, true>(g, src, dst, c, zchunk, ts, variant, s, queue);
 }
 
+
 template hipError_t launch_temporal_step<float>(const Geom &, const Fields<float> &, const Fields<float> &,
                                                 const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
+
+
+
 template hipError_t launch_temporal_step<f16>(const Geom &, const Fields<f16> &, const Fields<f16> &,
                                               const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
 
+
+
+
 template hipError_t launch_temporal_step<bf16>(const Geom &, const Fields<bf16> &, const Fields<bf16> &,
                                                const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);
+
+
 
 template hipError_t launch_temporal_step<f16c>(const Geom &, const Fields<f16c> &, const Fields<f16c> &,
                                                const Coefs<float> &, int, int, int, hipStream_t, bool, unsigned *);

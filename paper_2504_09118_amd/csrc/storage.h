@@ -182,12 +182,61 @@ __host__ __device__ inline float comp_inv_scale_bf16(unsigned short hbits)
     return bits_f32((unsigned)(127 + 7 + 8 - e + 127) << 23);
 }
 
+// The residual from the exact difference d = x - hi.
+__host__ __device__ inline signed char comp_residual_d(float d, float inv_scale)
+{
+    const float q = __builtin_fminf(__builtin_fmaxf(__builtin_rintf(d * inv_scale), -127.0f), 127.0f);
+    return (signed char)(int)q;
+}
+
 __host__ __device__ inline signed char comp_residual(float x, float hi, float inv_scale)
 {
     // exact scaling by a power of two; |q| <= 128 for a finite x, so the clamp only folds
     // the half-ulp case 128 onto 127 (a NaN x gives hi = NaN, whatever q holds)
     const float q = __builtin_fminf(__builtin_fmaxf(__builtin_rintf((x - hi) * inv_scale), -127.0f), 127.0f);
     return (signed char)(int)q;
+}
+
+// Pair forms of the compensated codec for the sweeps: the same values as dec / enc on each
+// element, with the two exponent fields handled by one packed 16-bit operation each
+// (v_pk_* integer forms) instead of two scalar ones.
+typedef unsigned short pk_u16x2 __attribute__((ext_vector_type(2)));
+
+// Exponent fields of two 16-bit values (u: a in the low half) moved to the low bits,
+// e = (u >> sh) & mask per half.
+__device__ inline pk_u16x2 pair_exp(unsigned u, int sh, unsigned short mask)
+{
+    pk_u16x2 h;
+    __builtin_memcpy(&h, &u, 4);
+    return (h >> (pk_u16x2)(unsigned short)sh) & (pk_u16x2)mask;
+}
+
+// Signed byte 0 / byte 1 of q as FP32, each one conversion reading its byte directly.
+__device__ inline float sbyte0_f32(unsigned q)
+{
+    float r;
+    __asm__("v_cvt_f32_i32_sdwa %0, sext(%1) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_0"
+            : "=v"(r)
+            : "v"(q));
+    return r;
+}
+
+__device__ inline float sbyte1_f32(unsigned q)
+{
+    float r;
+    __asm__("v_cvt_f32_i32_sdwa %0, sext(%1) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1"
+            : "=v"(r)
+            : "v"(q));
+    return r;
+}
+
+// FP32 powers of two whose exponent fields are the two halves of f (each < 256).
+__device__ inline void pair_pow2(pk_u16x2 f, float &lo, float &hi)
+{
+    unsigned u;
+    __builtin_memcpy(&u, &f, 4);
+    lo = bits_f32(u << 23);                  // the high half shifts out
+    hi = bits_f32((u >> 16) << 23);
 }
 
 template <>
@@ -217,9 +266,28 @@ struct Store<f16c> {
         _Float16 ha, hb;
         __builtin_memcpy(&ha, &ua, 2);
         __builtin_memcpy(&hb, &ub, 2);
-        const signed char qa = comp_residual(a, (float)ha, comp_inv_scale_f16(ua));
-        const signed char qb = comp_residual(b, (float)hb, comp_inv_scale_f16(ub));
+        // 1/s = 2^(33 - max(e, 1)): exponent field 160 - max(e, 1)
+        const pk_u16x2 e = __builtin_elementwise_max(pair_exp(hh, 10, 0x1f), (pk_u16x2)(unsigned short)1);
+        float ia, ib;
+        pair_pow2((pk_u16x2)(unsigned short)160 - e, ia, ib);
+        // x - hi is exact; fma(hi, -1, x) reads hi as FP16 in one mixed-precision instruction
+        const signed char qa = comp_residual_d(__builtin_fmaf((float)ha, -1.0f, a), ia);
+        const signed char qb = comp_residual_d(__builtin_fmaf((float)hb, -1.0f, b), ib);
         qq = (unsigned short)((unsigned char)qa | ((unsigned)(unsigned char)qb << 8));
+    }
+    // two values from the packed pair u (a low) and the packed residual bytes q
+    __device__ static void dec2(unsigned u, unsigned q, float &a, float &b)
+    {
+        // s = 2^(max(e, 1) - 33): exponent field max(e, 1) + 94
+        const pk_u16x2 e = __builtin_elementwise_max(pair_exp(u, 10, 0x1f), (pk_u16x2)(unsigned short)1);
+        float sa, sb;
+        pair_pow2(e + (pk_u16x2)(unsigned short)94, sa, sb);
+        const unsigned short ua = (unsigned short)(u & 0xffffu), ub = (unsigned short)(u >> 16);
+        _Float16 ha, hb;
+        __builtin_memcpy(&ha, &ua, 2);
+        __builtin_memcpy(&hb, &ub, 2);
+        a = (float)ha + sbyte0_f32(q) * sa;
+        b = (float)hb + sbyte1_f32(q) * sb;
     }
 };
 
@@ -239,10 +307,23 @@ struct Store<bf16c> {
     __device__ static void enc2(C a, C b, unsigned &hh, unsigned short &qq)
     {
         hh = pack2_bf16(a, b);
-        const unsigned short ua = (unsigned short)(hh & 0xffffu), ub = (unsigned short)(hh >> 16);
-        const signed char qa = comp_residual(a, bf16_to_float(bf16{ua}), comp_inv_scale_bf16(ua));
-        const signed char qb = comp_residual(b, bf16_to_float(bf16{ub}), comp_inv_scale_bf16(ub));
+        // 1/s = 2^(142 - max(e, 16)): exponent field 269 - max(e, 16), over 255 for e < 14,
+        // so the packed form takes 269 - max(e, 16) in 16 bits (at most 253)
+        const pk_u16x2 e = __builtin_elementwise_max(pair_exp(hh, 7, 0xff), (pk_u16x2)(unsigned short)16);
+        float ia, ib;
+        pair_pow2((pk_u16x2)(unsigned short)269 - e, ia, ib);
+        const signed char qa = comp_residual(a, bits_f32(hh << 16), ia);
+        const signed char qb = comp_residual(b, bits_f32(hh & 0xffff0000u), ib);
         qq = (unsigned short)((unsigned char)qa | ((unsigned)(unsigned char)qb << 8));
+    }
+    __device__ static void dec2(unsigned u, unsigned q, float &a, float &b)
+    {
+        // s = 2^(max(e, 16) - 142): exponent field max(e, 16) - 15
+        const pk_u16x2 e = __builtin_elementwise_max(pair_exp(u, 7, 0xff), (pk_u16x2)(unsigned short)16);
+        float sa, sb;
+        pair_pow2(e - (pk_u16x2)(unsigned short)15, sa, sb);
+        a = bits_f32(u << 16) + sbyte0_f32(q) * sa;
+        b = bits_f32(u & 0xffff0000u) + sbyte1_f32(q) * sb;
     }
 };
 
