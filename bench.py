@@ -134,10 +134,10 @@ def main() -> int:
     q = s.query()
     kernel = q["kernel"]
     steps_per_launch = int(q["steps_per_sweep"])
-    # the bandwidth probe and the serving leg run before the warm-up steps: after an idle spell
-    # the GPU's clocks take about 20 ms of stencil load to settle (the first ~10 sweeps run up
-    # to 20 % slow), and the serving leg is such a load, right before the timed region
-    probe = copy_probe(stream)
+    # the serving leg and then the bandwidth probe run before the warm-up steps: after an idle
+    # spell the GPU's clocks take about 20 ms of full load to settle (the first ~10 sweeps run
+    # up to 20 % slow); the probe's 42 back-to-back copies (about 34 ms) are such a load, right
+    # before the warm-up (the serving leg, at 0.9 of its saturation, leaves the GPU idle at times)
     serving = None
     if not args.no_serving:
         from paper_2504_09118_amd import serve
@@ -145,6 +145,7 @@ def main() -> int:
         serving = serve.bench_point(int(args.serving_budget_gib * 2 ** 30), load=args.serving_load,
                                     n_requests=args.serving_requests, stream=stream,
                                     log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+    probe = copy_probe(stream)
     s.step(args.warmup)
     s.sync()
     torch.cuda.synchronize()

@@ -270,9 +270,9 @@ struct Store<f16c> {
         const pk_u16x2 e = __builtin_elementwise_max(pair_exp(hh, 10, 0x1f), (pk_u16x2)(unsigned short)1);
         float ia, ib;
         pair_pow2((pk_u16x2)(unsigned short)160 - e, ia, ib);
-        // x - hi is exact; fma(hi, -1, x) reads hi as FP16 in one mixed-precision instruction
-        const signed char qa = comp_residual_d(__builtin_fmaf((float)ha, -1.0f, a), ia);
-        const signed char qb = comp_residual_d(__builtin_fmaf((float)hb, -1.0f, b), ib);
+        // x - hi is exact in FP32
+        const signed char qa = comp_residual_d(a - (float)ha, ia);
+        const signed char qb = comp_residual_d(b - (float)hb, ib);
         qq = (unsigned short)((unsigned char)qa | ((unsigned)(unsigned char)qb << 8));
     }
     // two values from the packed pair u (a low) and the packed residual bytes q
