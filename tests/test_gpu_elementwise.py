@@ -26,10 +26,23 @@ S = 0.5 / math.sqrt(3.0)
 DIMS = (150, 61, 37)   # 3 x 3 temporal tiles of 64 x 22 own cells, ragged in x and y
 
 
-def model_inputs(nx, ny, nz, seed, store):
+def wide(fields, draw, lo, hi):
+    """fields scaled node by node by 2^k, k uniform on the integers lo..hi, from the seeded
+    uniform draw (arrays of the same shapes, values in [-1, 1])."""
+    out = []
+    for x, u in zip(fields, draw):
+        k = np.floor(lo + (hi - lo + 1) * (u + 1.0) / 2.0).clip(lo, hi)
+        out.append(np.ldexp(x.astype(np.float64), k.astype(np.int64)).astype(np.float32))
+    return out
+
+
+def model_inputs(nx, ny, nz, seed, store, span=None):
     eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=6)
     e = ci.random_e(nx, ny, nz, seed=seed, dtype=np.float32)
     h = ci.random_h(nx, ny, nz, seed=seed + 1, dtype=np.float32)
+    if span is not None:
+        e = wide(e, ci.random_e(nx, ny, nz, seed=seed + 100), *span)
+        h = wide(h, ci.random_h(nx, ny, nz, seed=seed + 101), *span)
     start = oracle.make_state([store(a).astype(np.float64) for a in e], [store(a).astype(np.float64) for a in h])
     start = [a.astype(np.float32) for a in start]
     ce = [a.astype(np.float32) for a in oracle.round_to(oracle.coef_e(nx, ny, nz, 1.0, S, eps), np.float32)]
@@ -84,9 +97,14 @@ def test_fp32_state_equals_the_fma_model(kernel, tb, steps):
         assert bad == 0, f"{name}: {bad} nodes differ from the FP32 model (max |diff| {np.max(np.abs(g - m)):.3e})"
 
 
+# wide spans: every node scaled by 2^k, so the codecs meet FP16 subnormals (and, for BF16,
+# the residual-scale clamp of exponents under 16) and values up to 2^14
+SPANS = {"f16": (-26, 14), "f16c": (-26, 14), "bf16": (-120, 14), "bf16c": (-120, 14)}
+
+
 @pytest.mark.parametrize("storage", ["f16", "bf16", "f16c", "bf16c"])
-@pytest.mark.parametrize("steps", [3, 5])
-def test_16bit_sweeps_equal_the_storage_model(storage, steps):
+@pytest.mark.parametrize("steps,wide_span", [(3, False), (5, False), (3, True)])
+def test_16bit_sweeps_equal_the_storage_model(storage, steps, wide_span):
     """16-bit storage: one sweep of 3 steps (and a second, remainder sweep of 2) from a
     16-bit state, node by node against the model that rounds the FP32 state once per sweep.
     The model is exact (FMA included), so every node must be equal; the report also gives
@@ -96,7 +114,7 @@ def test_16bit_sweeps_equal_the_storage_model(storage, steps):
 
     nx, ny, nz = DIMS
     store = steps_of_storage(storage)
-    eps, e, h, start, ce, ch = model_inputs(nx, ny, nz, 43, store)
+    eps, e, h, start, ce, ch = model_inputs(nx, ny, nz, 43, store, SPANS[storage] if wide_span else None)
     with Solver(nx, ny, nz, 1.0, S, eps_r=eps, storage=storage, kernel="temporal", tb_steps=3) as s:
         s.set_fields(e, h)
         s.step(steps)
