@@ -111,7 +111,8 @@ typedef struct {
     int storage;        /* fdtd_dtype of device fields: FDTD_F32 (default), FDTD_F64, FDTD_F16, FDTD_BF16,
                            FDTD_F16C, FDTD_BF16C (16-bit based storage runs the temporal kernel only) */
     int kernel;         /* fdtd_kernel, default FDTD_KERNEL_AUTO */
-    int tb_steps;       /* steps per sweep for FDTD_KERNEL_TEMPORAL (0: library default) */
+    int tb_steps;       /* steps per sweep for FDTD_KERNEL_TEMPORAL, 1..4 (0: library default:
+                           4 for FP32 fields without per-node Ch, else 3) */
     int device;         /* HIP device ordinal, default 0 */
     void *stream;       /* hipStream_t to enqueue on; NULL: the library creates its own */
     void *arena;        /* caller-owned device memory for all device state; NULL: hipMalloc */
@@ -279,7 +280,7 @@ int fdtd_query(fdtd_t h, long long out[8]);
  */
 typedef struct {
     int kernel;         /* FDTD_KERNEL_PLAIN .. FDTD_KERNEL_TEMPORAL */
-    int tb_steps;       /* steps per sweep (temporal: 1..3; others 1) */
+    int tb_steps;       /* steps per sweep (temporal: 1..4, 1..3 for variant 1; others 1) */
     int variant;        /* tile shape: slab 0..3 = (cells per lane, waves) (2,16) (2,8) (1,16) (1,8);
                            temporal 0..1 = 64 columns x 2 rows per wave, 128 columns x 1 row per wave */
     int zchunks;        /* z-ranges per launch (fused, slab, temporal), 1..nz */

@@ -540,8 +540,8 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         return fail(FDTD_E_UNSUPPORTED, "the temporal kernel is not built for FP64 storage");
     if (is16(o->storage) && kern != FDTD_KERNEL_TEMPORAL)
         return fail(FDTD_E_UNSUPPORTED, "16-bit storage is built for the temporal kernel only");
-    if (kern == FDTD_KERNEL_TEMPORAL && (o->tb_steps < 0 || o->tb_steps > 3))
-        return fail(FDTD_E_ARG, "tb_steps must be 1..3 (0: default 3), got %d", o->tb_steps);
+    if (kern == FDTD_KERNEL_TEMPORAL && (o->tb_steps < 0 || o->tb_steps > 4))
+        return fail(FDTD_E_ARG, "tb_steps must be 1..4 (0: the default), got %d", o->tb_steps);
     {
         // the sweeps address one padded x-y plane with 32-bit byte offsets and mark a dropped
         // access with an offset of 2^31, so a plane must stay below 2^31 bytes
@@ -649,6 +649,13 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         h->zchunk = zc;
     }
     h->tvariant = env_int("FDTD_TEMPORAL_VARIANT", 0);
+    if (kern == FDTD_KERNEL_TEMPORAL && o->tb_steps == 0)
+        // default steps per sweep: 4 for FP32 fields (512^3: 258 Gcell/s against 226 at 3);
+        // 3 where a fourth stage costs more than it saves (16-bit storage: its conversions;
+        // per-node Ch: a third coefficient pipeline spills registers)
+        h->tb = o->storage == FDTD_F32 && !h->ch_arr && h->tvariant == 0 ? 4 : 3;
+    if (h->tb > 3)
+        h->tvariant = 0;  // one row per wave is built for 1..3 steps per sweep
     h->tzchunk = env_int("FDTD_TZCHUNKS", 0);
     if (h->tzchunk <= 0) {
         // One temporal workgroup per CU, and a workgroup's time is close to proportional to the
@@ -983,10 +990,12 @@ int validate_schedule(fdtd_t h, const fdtd_schedule *sc)
         return fail(FDTD_E_UNSUPPORTED, "16-bit storage is built for the temporal kernel only");
     if (h->storage == FDTD_F64 && sc->kernel == FDTD_KERNEL_TEMPORAL)
         return fail(FDTD_E_UNSUPPORTED, "the temporal kernel is not built for FP64 storage");
-    if (sc->kernel == FDTD_KERNEL_TEMPORAL && (sc->tb_steps < 1 || sc->tb_steps > 3))
-        return fail(FDTD_E_ARG, "tb_steps must be 1..3, got %d", sc->tb_steps);
+    if (sc->kernel == FDTD_KERNEL_TEMPORAL && (sc->tb_steps < 1 || sc->tb_steps > 4))
+        return fail(FDTD_E_ARG, "tb_steps must be 1..4, got %d", sc->tb_steps);
     if (sc->kernel == FDTD_KERNEL_TEMPORAL && (sc->variant < 0 || sc->variant > 1))
         return fail(FDTD_E_ARG, "temporal variant must be 0..1, got %d", sc->variant);
+    if (sc->kernel == FDTD_KERNEL_TEMPORAL && sc->variant == 1 && sc->tb_steps > 3)
+        return fail(FDTD_E_UNSUPPORTED, "temporal variant 1 is built for tb_steps 1..3");
     if (sc->kernel == FDTD_KERNEL_SLAB && (sc->variant < 0 || sc->variant > 3))
         return fail(FDTD_E_ARG, "slab variant must be 0..3, got %d", sc->variant);
     if (sc->kernel == FDTD_KERNEL_SLAB && h->storage == FDTD_F64 && sc->variant != 3)
@@ -1042,11 +1051,12 @@ std::vector<fdtd_schedule> schedule_candidates(fdtd_t h)
         tzcs.push_back(h->tzchunk);
     // 16-bit storage rounds the state at the end of every sweep, so the steps per sweep set
     // the numerics: the search keeps the solver's own tb there and varies only the tiling
-    const int tb_lo = is16(h->storage) ? h->tb : 1, tb_hi = is16(h->storage) ? h->tb : 3;
+    const int tb_lo = is16(h->storage) ? h->tb : 1, tb_hi = is16(h->storage) ? h->tb : 4;
     if (h->storage != FDTD_F64)
         for (int tb = tb_lo; tb <= tb_hi; ++tb)
             for (int v = 0; v < 2; ++v)
-                for (int zc : tzcs) add(FDTD_KERNEL_TEMPORAL, tb, v, zc);
+                if (v == 0 || tb <= 3)
+                    for (int zc : tzcs) add(FDTD_KERNEL_TEMPORAL, tb, v, zc);
     return out;
 }
 

@@ -6,7 +6,7 @@
 //
 // Structure (per workgroup of 16 waves: an x-y tile of W own columns x
 // (R - 2 TS) own rows, marching a z-chunk; the default tile is 64 x 26 for
-// TS = 2, 64 x 22 for TS = 3):
+// TS = 2, 64 x 22 for TS = 3, 64 x 20 for TS = 4):
 //   - stage s = 1..TS computes step n+s on plane p_s = k - (s-1) at loop
 //     index k: H^{n+s-1/2}(p_s) from E^{n+s-1} at planes p_s and p_s+1, then
 //     E^{n+s}(p_s) from H^{n+s-1/2} at planes p_s and p_s-1. Stage s-1 has
@@ -226,7 +226,7 @@ struct TShape {
     static constexpr int W = LPR * V;                    // own columns
     static constexpr int NVH = (TS + V - 1) / V;         // halo vectors per side
     static constexpr int HX = NVH * V;                   // halo columns per side
-    static constexpr int NHW = (RPW == 2 && TS == 3) ? 2 : 1;  // halo waves
+    static constexpr int NHW = (RPW == 2 && TS >= 3) ? 2 : 1;  // halo waves
     static constexpr int NRW = 16 - NHW;                 // row waves
     static constexpr int R = NRW * RPW;                  // rows (own rows: R - 2 TS)
     static_assert(2 * NVH * R <= 64 * NHW, "halo lanes do not fit");
@@ -757,16 +757,18 @@ hipError_t launch_shape(const Geom &g, const Fields<T> &src, const Fields<T> &ds
     case 1: return launch_ts<T, 1, 2, NT>(g, src, dst, c, zchunk, s, queue);
     case 2: return launch_ts<T, 2, 2, NT>(g, src, dst, c, zchunk, s, queue);
     case 3: return launch_ts<T, 3, 2, NT>(g, src, dst, c, zchunk, s, queue);
+    case 4: return launch_ts<T, 4, 2, NT>(g, src, dst, c, zchunk, s, queue);
     default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-// variant 0: two rows per wave (64 x ~26 tiles); variant 1: one row per wave (128 x ~11 tiles)
+// variant 0: two rows per wave (64 x ~26 tiles, TS = 1..4); variant 1: one row per wave
+// (128 x ~11 tiles, TS = 1..3)
 int temporal_own_rows(int ts, int variant)
 {
-    return variant == 1 ? 15 - 2 * ts : (ts == 3 ? 28 : 30) - 2 * ts;
+    return variant == 1 ? 15 - 2 * ts : (ts >= 3 ? 28 : 30) - 2 * ts;
 }
 
 int temporal_width(int variant) { return variant == 1 ? 128 : 64; }

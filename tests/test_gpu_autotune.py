@@ -96,6 +96,10 @@ def test_set_schedule_validation():
         s.set_schedule("slab", 1, 3, 2)
     with P.Solver(16, 16, 16, 1.0, S) as s:
         with pytest.raises(P.FdtdError):
-            s.set_schedule("temporal", 4, 0, 1)
+            s.set_schedule("temporal", 5, 0, 1)
+        with pytest.raises(P.FdtdError):
+            s.set_schedule("temporal", 4, 1, 1)  # one row per wave: 1..3 steps per sweep
+        s.set_schedule("temporal", 4, 0, 1)
+        assert s.schedule["tb_steps"] == 4
         with pytest.raises(P.FdtdError):
             s.set_schedule("fused", 1, 0, 0)

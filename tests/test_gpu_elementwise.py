@@ -77,8 +77,8 @@ def ulp16(x, storage):
     return np.ldexp(1.0, e - 127 - 7)
 
 
-@pytest.mark.parametrize("kernel,tb,steps", [("auto", 0, 20), ("temporal", 2, 7), ("slab", 0, 5),
-                                             ("plain", 0, 5)])
+@pytest.mark.parametrize("kernel,tb,steps", [("auto", 0, 20), ("temporal", 2, 7), ("temporal", 4, 11),
+                                             ("temporal", 3, 11), ("slab", 0, 5), ("plain", 0, 5)])
 def test_fp32_state_equals_the_fma_model(kernel, tb, steps):
     """FP32 storage: the device state after several steps equals the model bit for bit."""
     from paper_2504_09118_amd import Solver

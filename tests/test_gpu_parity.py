@@ -141,7 +141,8 @@ def test_parity_ragged_medium(kernel):
 
 
 def test_kernels_bitwise_equal(monkeypatch):
-    # 41 steps: tb = 3 leaves a remainder sweep of 2 steps, tb = 2 one of 1
+    # 41 steps: tb = 3 leaves a remainder sweep of 2 steps, tb = 2 and tb = 4 one of 1
+    # (tb = 4 is built for variant 0 only: with variant 1 asked for, the solver uses variant 0)
     nx, ny, nz, steps = 70, 19, 37, 41
     eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=8)
     e = ci.random_e(nx, ny, nz, seed=5, dtype=np.float32)
@@ -158,7 +159,7 @@ def test_kernels_bitwise_equal(monkeypatch):
         outs[(kernel, zc, var)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel=kernel)
     for tv in ("0", "1"):
         monkeypatch.setenv("FDTD_TEMPORAL_VARIANT", tv)
-        for tb in (1, 2, 3):
+        for tb in (1, 2, 3, 4):
             for tzc in ("1", "2", "5"):
                 monkeypatch.setenv("FDTD_TZCHUNKS", tzc)
                 outs[("temporal", tv, tb, tzc)] = run_gpu(nx, ny, nz, e, h, eps, None, steps, kernel="temporal",
@@ -169,7 +170,7 @@ def test_kernels_bitwise_equal(monkeypatch):
             assert np.array_equal(a, b), key
 
 
-@pytest.mark.parametrize("tb", [1, 2, 3])
+@pytest.mark.parametrize("tb", [1, 2, 3, 4])
 def test_temporal_parity_ragged(tb):
     # odd step count: tb-step sweeps plus single-step remainder
     nx, ny, nz, steps = 133, 40, 71, 301
@@ -308,7 +309,8 @@ def test_parity_256_cavity_1000_steps():
 
 
 DEGENERATE_DIMS = [(2, 2, 2), (2, 3, 65), (65, 2, 2), (3, 67, 2), (129, 2, 3)]
-SCHEDULES = [("plain", 0), ("fused", 0), ("slab", 0), ("temporal", 1), ("temporal", 2), ("temporal", 3)]
+SCHEDULES = [("plain", 0), ("fused", 0), ("slab", 0), ("temporal", 1), ("temporal", 2), ("temporal", 3),
+             ("temporal", 4)]
 
 
 @pytest.mark.parametrize("dims", DEGENERATE_DIMS)
@@ -350,7 +352,7 @@ def test_zero_steps_leave_the_state_unchanged(kernel):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("kernel,tb", [("slab", 0), ("temporal", 3), ("temporal", 1)])
+@pytest.mark.parametrize("kernel,tb", [("slab", 0), ("temporal", 4), ("temporal", 3), ("temporal", 1)])
 def test_store_policy_gives_the_same_bits(monkeypatch, kernel, tb):
     """The sweeps are built with default and non-temporal store policies (chosen by state
     size); both give the same bits."""
@@ -385,7 +387,7 @@ def test_wall_normal_h_and_walls_keep_their_bits():
     eps = ci.sphere_eps(nx, ny, nz, seed=53, nspheres=4)
     for medium in (None, eps):
         plain = run_gpu(nx, ny, nz, e, h, medium, None, steps, kernel="plain")
-        for tb in (1, 2, 3):
+        for tb in (1, 2, 3, 4):
             got = run_gpu(nx, ny, nz, e, h, medium, None, steps, kernel="temporal", tb_steps=tb)
             for a, b in zip(got, plain):
                 assert np.array_equal(a, b) and np.array_equal(np.signbit(a), np.signbit(b)), tb
@@ -480,7 +482,7 @@ def test_schedule_changes_between_sweeps_keep_the_bits():
     plain = run_gpu(nx, ny, nz, e, h, eps, None, 21, kernel="plain")
     with _solver(nx, ny, nz, 1.0, S, eps_r=eps, kernel="temporal", tb_steps=3) as s:
         s.set_fields(e, h)
-        for tb, zc, n in ((3, 0, 6), (2, 0, 4), (1, 0, 2), (3, 5, 3), (3, 1, 6)):
+        for tb, zc, n in ((3, 0, 6), (2, 0, 4), (1, 0, 2), (4, 0, 4), (3, 5, 3), (4, 3, 2)):
             if zc:
                 s.set_schedule("temporal", tb_steps=tb, zchunks=zc)
             else:
@@ -493,14 +495,14 @@ def test_schedule_changes_between_sweeps_keep_the_bits():
 
 def test_full_size_default_schedule_equals_plain_bitwise():
     """512^3 with spherical inclusions, the benchmark's launch configuration (temporal
-    sweeps of 3 steps from the per-XCD tile queues, 4 z-chunks), 32 steps (ten 3-step sweeps
-    and a 2-step remainder sweep): the whole state equals the plain two-kernel schedule bit
-    for bit. Both runs stay on the GPU; the comparison runs there too."""
+    sweeps of 4 steps from the per-XCD tile queues), 34 steps (eight 4-step sweeps and a
+    2-step remainder sweep): the whole state equals the plain two-kernel schedule bit for
+    bit. Both runs stay on the GPU; the comparison runs there too."""
     import torch
 
     from paper_2504_09118_amd import Solver, field_shapes
 
-    n, steps = 512, 32
+    n, steps = 512, 34
     eps = ci.sphere_eps(n, n, n, seed=33)
     stream = torch.cuda.Stream()
     outs = {}
@@ -510,7 +512,7 @@ def test_full_size_default_schedule_equals_plain_bitwise():
             s.step(steps)
             q = s.query()
             if kernel == "auto":
-                assert q["kernel"] == "temporal" and q["steps_per_sweep"] == 3 and q["sweeps"] == 11
+                assert q["kernel"] == "temporal" and q["steps_per_sweep"] == 4 and q["sweeps"] == 9
             out = [torch.empty(sh, dtype=torch.float32, device="cuda") for sh in field_shapes(n, n, n)]
             s.get_fields_device(out)
             s.sync()
