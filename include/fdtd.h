@@ -410,7 +410,7 @@ typedef struct fdtd_pool *fdtd_pool_t;
 typedef struct {
     size_t hbm_budget; /* device bytes for request state (>= 1 MiB); with arena: its size */
     int device;        /* HIP device ordinal */
-    int tb_steps;      /* steps per batched sweep, 1..3 (0: 3) */
+    int tb_steps;      /* steps per batched sweep, 1..4 (0: 4; requests with per-node Ch take at most 3) */
     int max_active;    /* most admitted requests at once, 1..65536 (0: 256) */
     int backfill;      /* 0: strict FIFO admission; 1: requests that fit may pass the queue head */
     void *stream;      /* hipStream_t for all request work; NULL: the pool creates one */
@@ -455,7 +455,7 @@ typedef struct {
     int failed;
 } fdtd_pool_counters;
 
-/* Defaults: tb_steps 3, max_active 256, backfill 0, device 0; hbm_budget must be set. */
+/* Defaults: tb_steps 4, max_active 256, backfill 0, device 0; hbm_budget must be set. */
 int fdtd_pool_opts_default(fdtd_pool_opts *opts);
 
 /* Device bytes a request holds while admitted (fields double-buffered, per-node

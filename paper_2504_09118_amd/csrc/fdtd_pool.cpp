@@ -383,7 +383,9 @@ bool launch_round(fdtd_pool_t p)
             last.push_back(r);
             continue;
         }
-        const int ts = (int)std::min<long long>(p->tb, r->remaining);
+        // requests with per-node Ch take at most 3 steps per sweep (a fourth stage spills
+        // registers there); the steps per sweep never change an FP32 request's bits
+        const int ts = (int)std::min<long long>(r->ch_arr ? std::min(p->tb, 3) : p->tb, r->remaining);
         groups[ts * 4 + (r->ce_arr ? 2 : 0) + (r->ch_arr ? 1 : 0)].push_back(r);
     }
     for (auto &kv : groups) {
@@ -582,7 +584,7 @@ int fdtd_pool_opts_default(fdtd_pool_opts *o)
     if (!o)
         return pfail(FDTD_E_ARG, "NULL opts");
     memset(o, 0, sizeof *o);
-    o->tb_steps = 3;
+    o->tb_steps = 4;
     o->max_active = 256;
     return FDTD_OK;
 }
@@ -605,9 +607,9 @@ int fdtd_pool_create(const fdtd_pool_opts *opts, fdtd_pool_t *out)
         return pfail(FDTD_E_ARG, "hbm_budget must be >= 1 MiB (got %zu)", opts->hbm_budget);
     if (opts->arena && opts->hbm_budget == 0)
         return pfail(FDTD_E_ARG, "arena given with hbm_budget = 0");
-    const int tb = opts->tb_steps ? opts->tb_steps : 3;
-    if (tb < 1 || tb > 3)
-        return pfail(FDTD_E_ARG, "tb_steps must be 1..3 (0: 3), got %d", opts->tb_steps);
+    const int tb = opts->tb_steps ? opts->tb_steps : 4;
+    if (tb < 1 || tb > 4)
+        return pfail(FDTD_E_ARG, "tb_steps must be 1..4 (0: 4), got %d", opts->tb_steps);
     const int max_active = opts->max_active ? opts->max_active : 256;
     if (max_active < 1 || max_active > 65536)
         return pfail(FDTD_E_ARG, "max_active must be 1..65536, got %d", opts->max_active);

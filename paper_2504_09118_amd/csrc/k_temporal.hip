@@ -804,6 +804,7 @@ hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, 
         case 1: FDTD_BATCH_Q(1); break;
         case 2: FDTD_BATCH_Q(2); break;
         case 3: FDTD_BATCH_Q(3); break;
+        case 4: FDTD_BATCH_Q(4); break;
         default: return hipErrorInvalidValue;
         }
 #undef FDTD_BATCH_Q
@@ -825,6 +826,7 @@ hipError_t launch_temporal_batch(const BatchEntry *table, int nreq, int ntiles, 
     case 1: FDTD_BATCH_TS(1); break;
     case 2: FDTD_BATCH_TS(2); break;
     case 3: FDTD_BATCH_TS(3); break;
+    case 4: FDTD_BATCH_TS(4); break;
     default: return hipErrorInvalidValue;
     }
 #undef FDTD_BATCH_TS

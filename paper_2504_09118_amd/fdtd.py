@@ -450,11 +450,11 @@ class Pool:
 
     hbm_budget: device bytes for all admitted requests' state. The pool's loop
     thread (in the library) admits requests by memory, advances every admitted
-    request by up to tb_steps steps per batched launch, and retires finished
-    ones. stream: as for Solver; None lets the pool create one.
+    request by up to tb_steps steps per batched launch (0: the library default,
+    4), and retires finished ones. stream: as for Solver; None lets the pool create one.
     """
 
-    def __init__(self, hbm_budget: int, tb_steps: int = 3, max_active: int = 256, backfill: bool = False,
+    def __init__(self, hbm_budget: int, tb_steps: int = 0, max_active: int = 256, backfill: bool = False,
                  stream=None, device: int = 0):
         self._lib = load_library()
         self._h = ctypes.c_void_p(None)

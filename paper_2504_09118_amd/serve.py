@@ -107,7 +107,7 @@ def run_poisson(pool: Pool, rate: float, n: int, seed: int, dims=DIMS, steps=STE
 
 
 def serving_sweep(budget_bytes: int, fractions, n_per_rate: int = 200, n_burst: int = 100, seed: int = 4,
-                  tb_steps: int = 3, backfill: bool = False, stream=None, log=None) -> dict:
+                  tb_steps: int = 0, backfill: bool = False, stream=None, log=None) -> dict:
     """Saturation from a burst, then a Poisson run at each fraction of it."""
     with Pool(budget_bytes, tb_steps=tb_steps, backfill=backfill, stream=stream) as pool:
         run_burst(pool, 8, seed + 1000)  # warm-up: code objects, allocator, clocks
@@ -177,7 +177,7 @@ def main() -> None:
     ap.add_argument("--rates", default="0.25,0.5,0.75,0.9,1.0,1.2", help="fractions of the saturation rate")
     ap.add_argument("--requests", type=int, default=200, help="requests per rate")
     ap.add_argument("--burst", type=int, default=100, help="requests of the saturation burst")
-    ap.add_argument("--tb-steps", type=int, default=3)
+    ap.add_argument("--tb-steps", type=int, default=0, help="steps per batched sweep (0: the library default, 4)")
     ap.add_argument("--backfill", action="store_true")
     ap.add_argument("--seed", type=int, default=4)
     args = ap.parse_args()

@@ -154,13 +154,13 @@ def test_pool_create_validates_options():
     lib = F.load_library()
     opts = F._PoolOpts()
     assert lib.fdtd_pool_opts_default(ctypes.byref(opts)) == F.OK
-    assert opts.tb_steps == 3 and opts.max_active == 256 and opts.backfill == 0 and opts.hbm_budget == 0
+    assert opts.tb_steps == 4 and opts.max_active == 256 and opts.backfill == 0 and opts.hbm_budget == 0
     h = ctypes.c_void_p(None)
     assert lib.fdtd_pool_create(ctypes.byref(opts), ctypes.byref(h)) == F.E_ARG  # no budget
     opts.hbm_budget = 1 << 30
-    opts.tb_steps = 4
+    opts.tb_steps = 5
     assert lib.fdtd_pool_create(ctypes.byref(opts), ctypes.byref(h)) == F.E_ARG
-    opts.tb_steps = 3
+    opts.tb_steps = 4
     opts.max_active = -2
     assert lib.fdtd_pool_create(ctypes.byref(opts), ctypes.byref(h)) == F.E_ARG
     assert not h.value
