@@ -19,14 +19,14 @@ pytestmark = pytest.mark.gpu
 S = 0.5 / math.sqrt(3.0)
 
 
-def _pair(nx, ny, nz, seed, storage="f32", eps=True):
+def _pair(nx, ny, nz, seed, storage="f32", eps=True, tb=3):
     from paper_2504_09118_amd import Solver
 
     eps_r = ci.sphere_eps(nx, ny, nz, seed=seed, nspheres=5) if eps else None
     e = ci.random_e(nx, ny, nz, seed=seed, dtype=np.float32)
     h = ci.random_h(nx, ny, nz, seed=seed + 1, dtype=np.float32)
-    a = Solver(nx, ny, nz, 1.0, S, eps_r=eps_r, storage=storage, kernel="temporal", tb_steps=3)
-    b = Solver(nx, ny, nz, 1.0, S, eps_r=eps_r, storage=storage, kernel="temporal", tb_steps=3)
+    a = Solver(nx, ny, nz, 1.0, S, eps_r=eps_r, storage=storage, kernel="temporal", tb_steps=tb)
+    b = Solver(nx, ny, nz, 1.0, S, eps_r=eps_r, storage=storage, kernel="temporal", tb_steps=tb)
     a.set_fields(e, h)
     b.set_fields(e, h)
     return a, b
@@ -45,11 +45,12 @@ def _same(a, b, what):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), f"{what}: {name}"
 
 
-def test_noalloc_steps_equal_fdtd_step_on_two_calls_second_smaller():
-    a1, b1 = _pair(150, 61, 37, 7)
-    a2, b2 = _pair(40, 30, 20, 9)
+@pytest.mark.parametrize("tb", [3, 4])
+def test_noalloc_steps_equal_fdtd_step_on_two_calls_second_smaller(tb):
+    a1, b1 = _pair(150, 61, 37, 7, tb=tb)
+    a2, b2 = _pair(40, 30, 20, 9, tb=tb)
     try:
-        _noalloc(a1, 7)          # two 3-step sweeps and a 1-step remainder sweep
+        _noalloc(a1, 7)          # tb-step sweeps and a remainder sweep
         b1.step(7)
         _same(a1, b1, "first call, 150x61x37")
         _noalloc(a2, 5)          # a smaller cavity on the same counters
