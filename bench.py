@@ -30,10 +30,12 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 STORAGE_LABEL = {"f32": "FP32", "f16": "FP16", "bf16": "BF16", "f16c": "FP16+int8 residual",
                  "bf16c": "BF16+int8 residual"}
-FIELD_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "f16c": 3, "bf16c": 3}
+# compensated storage: the 16-bit value and a third of the 4-byte residual record its
+# node's E (or H) components share
+FIELD_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "f16c": 2 + 4 / 3, "bf16c": 2 + 4 / 3}
 
 
-def algorithmic_bytes_per_cell_step(kernel: str, ce_arrays: bool, ch_arrays: bool, field_bytes: int = 4,
+def algorithmic_bytes_per_cell_step(kernel: str, ce_arrays: bool, ch_arrays: bool, field_bytes: float = 4,
                                     coef_bytes: int = 4) -> float:
     """Bytes one sweep must move per cell.
 

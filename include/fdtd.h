@@ -69,8 +69,9 @@ typedef enum {
  * hi, the rounding residual of the FP32 value x it stands for: q = rint((x -
  * hi) / s) in [-127, 127] as an int8, s = ulp(hi) / 256 (a power of two from
  * hi's exponent). The value is hi + q s, exact in FP32 and within ulp(hi)/512
- * of x: 3 bytes per value, about 2^-20 (FP16) or 2^-17 (BF16) relative per
- * store instead of 2^-11 or 2^-8. Built for the temporal kernel.
+ * of x, about 2^-20 (FP16) or 2^-17 (BF16) relative per store instead of 2^-11
+ * or 2^-8. The three residuals of a node's E (or H) components share one 4-byte
+ * record on the device: 2 + 4/3 bytes per value. Built for the temporal kernel.
  */
 typedef enum {
     FDTD_F64 = 0,

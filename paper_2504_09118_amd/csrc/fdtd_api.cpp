@@ -51,8 +51,11 @@ Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool 
     g.box = (long long)up((size_t)g.plane * g.pz + 2 * kGuardElems, 64);
     p.fesz = (size_t)fesz;
     p.cesz = fesz == 8 ? 8 : 4;  // 16-bit fields keep FP32 coefficients
-    p.fbox_bytes = up((size_t)g.box * p.fesz, 256) + (comp ? up((size_t)g.box, 256) : 0);
-    g.lo_off = comp ? (long long)up((size_t)g.box * p.fesz, 256) + kGuardElems - (long long)kGuardElems * fesz : 0;
+    // compensated storage: every box has room for a record box (kRecBytes per element, after
+    // the 16-bit values); the E records use Ex's, the H records Hx's
+    p.fbox_bytes = up((size_t)g.box * p.fesz, 256) + (comp ? up((size_t)g.box * kRecBytes, 256) : 0);
+    g.lo_off = comp ? (long long)up((size_t)g.box * p.fesz, 256) + (long long)kGuardElems * (kRecBytes - fesz) : 0;
+    g.lo_step = comp ? (long long)p.fbox_bytes - 1 : 0;
     p.cbox_bytes = up((size_t)g.box * p.cesz, 256);
     size_t off = 0;
     for (int b = 0; b < 2; ++b)

@@ -31,8 +31,14 @@ struct Geom {
     int px, py, pz;
     long long plane;  // px * py
     long long box;    // elements reserved per component box (incl. guards, 64-aligned)
-    long long lo_off; // compensated 16-bit storage: byte offset from a box's element 0 to
-                      // its residual box's element 0 (0 otherwise)
+    // compensated 16-bit storage (0 otherwise): the residual records of the E components
+    // sit in Ex's box after its 16-bit values, those of H in Hx's box; lo_off is the byte
+    // distance from Ex's (Hx's) element 0 to the record of element 0, and lo_step + 1 the
+    // distance between the boxes of one state (Ey = Ex + lo_step + 1 bytes, and so on)
+    long long lo_off;
+    long long lo_step;
+    // byte distance from component q's element 0 to its residual byte of element 0
+    __host__ __device__ long long lo_rec(int q) const { return lo_off - (long long)(q % 3) * lo_step; }
     __host__ __device__ long long at(int i, int j, int k) const
     {
         return (long long)i + (long long)px * ((long long)j + (long long)py * k);
@@ -155,7 +161,8 @@ struct Plan {
 };
 
 // fesz: 8, 4 or 2 bytes; coefficients are FP64 for FP64 fields, else FP32. comp: each
-// field box also carries an int8 residual box (compensated 16-bit storage).
+// field box also has room for a box of residual records (compensated 16-bit storage;
+// the E records use Ex's, the H records Hx's, see Geom::lo_off).
 Plan make_plan(int nx, int ny, int nz, int fesz, bool ce_arr, bool ch_arr, bool aux, bool comp = false);
 
 // Seeded random state (E ~ U[-1,1] from a counter-based SplitMix64, PEC walls,

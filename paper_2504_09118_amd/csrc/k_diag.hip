@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(kBlock)
         }
         for (int q = 0; q < 3; ++q) {
             if (!ex[q]) continue;
-            double e = val(f.f[q], o, g.lo_off);
+            double e = val(f.f[q], o, g.lo_rec(q));
             if (!isfinite(e)) bad += 1;
             se += e * e;
             const bool wall = e_tan(q, i, j, k, nx, ny, nz);
@@ -78,11 +78,11 @@ __global__ void __launch_bounds__(kBlock)
                 if (ce != 0.0) w += e * e / ce;
             }
         }
-        const double Ex0 = ex[0] ? val(f.f[0], o, g.lo_off) : 0.0, Ey0 = ex[1] ? val(f.f[1], o, g.lo_off) : 0.0,
-                     Ez0 = ex[2] ? val(f.f[2], o, g.lo_off) : 0.0;
+        const double Ex0 = ex[0] ? val(f.f[0], o, g.lo_rec(0)) : 0.0, Ey0 = ex[1] ? val(f.f[1], o, g.lo_rec(1)) : 0.0,
+                     Ez0 = ex[2] ? val(f.f[2], o, g.lo_rec(2)) : 0.0;
         for (int q = 3; q < 6; ++q) {
             if (!ex[q]) continue;
-            double h = val(f.f[q], o, g.lo_off);
+            double h = val(f.f[q], o, g.lo_rec(q));
             if (!isfinite(h)) bad += 1;
             sh += h * h;
             if (h_normal(q, i, j, k, nx, ny, nz)) continue;
@@ -90,11 +90,11 @@ __global__ void __launch_bounds__(kBlock)
             if (ch == 0.0) continue;
             double d;
             if (q == 3)
-                d = (val(f.f[1], o + P, g.lo_off) - Ey0) - (val(f.f[2], o + px, g.lo_off) - Ez0);
+                d = (val(f.f[1], o + P, g.lo_rec(1)) - Ey0) - (val(f.f[2], o + px, g.lo_rec(2)) - Ez0);
             else if (q == 4)
-                d = (val(f.f[2], o + 1, g.lo_off) - Ez0) - (val(f.f[0], o + P, g.lo_off) - Ex0);
+                d = (val(f.f[2], o + 1, g.lo_rec(2)) - Ez0) - (val(f.f[0], o + P, g.lo_rec(0)) - Ex0);
             else
-                d = (val(f.f[0], o + px, g.lo_off) - Ex0) - (val(f.f[1], o + 1, g.lo_off) - Ey0);
+                d = (val(f.f[0], o + px, g.lo_rec(0)) - Ex0) - (val(f.f[1], o + 1, g.lo_rec(1)) - Ey0);
             const double hn = h + ch * d;
             w += h * hn / ch;
         }
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(kBlock)
                 if (h_normal(q, ii, jj, kk, nx, ny, nz)) return 0.0;
                 const long long oo = g.at(ii, jj, kk);
                 const double ch = coef_at(c.ch[q - 3], c.ch_s, false, oo);
-                return ch != 0.0 ? val(f.f[q], oo, g.lo_off) / ch : 0.0;
+                return ch != 0.0 ? val(f.f[q], oo, g.lo_rec(q)) / ch : 0.0;
             };
             const double dv = (b(3, i + 1, j, k) - b(3, i, j, k)) + (b(4, i, j + 1, k) - b(4, i, j, k)) +
                               (b(5, i, j, k + 1) - b(5, i, j, k));

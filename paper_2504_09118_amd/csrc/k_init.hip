@@ -52,9 +52,9 @@ __global__ void __launch_bounds__(kBlock) k_init_random(Geom g, int field, int X
         }
     }
     const long long o = g.at(i, j, k);
-    put_elem(dst, g.lo_off, o, v);
+    put_elem(dst, g.lo_rec(field), o, v);
     if (dst2)
-        put_elem(dst2, g.lo_off, o, v);
+        put_elem(dst2, g.lo_rec(field), o, v);
 }
 
 }  // namespace

@@ -61,13 +61,13 @@ __global__ void __launch_bounds__(kBlock) k_pack(Geom g, int field, int X, int Y
     if (h_wall_normal(field, i, j, k, g.nx, g.ny, g.nz) && v == 0)
         v = 0;
     long long o = g.at(i, j, k);
-    put_elem(dst, g.lo_off, o, v);
+    put_elem(dst, g.lo_rec(field), o, v);
     if (dst2)
-        put_elem(dst2, g.lo_off, o, v);
+        put_elem(dst2, g.lo_rec(field), o, v);
 }
 
 template <typename T, typename S>
-__global__ void __launch_bounds__(kBlock) k_unpack(Geom g, int X, int Y, long long n,
+__global__ void __launch_bounds__(kBlock) k_unpack(Geom g, int field, int X, int Y, long long n,
                                                    const T *__restrict__ src, S *__restrict__ dst, double scale)
 {
     long long l = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kBlock) k_unpack(Geom g, int X, int Y, long lo
         return;
     int i, j, k;
     unflatten(l, X, Y, i, j, k);
-    dst[l] = (S)((double)get_elem(src, g.lo_off, g.at(i, j, k)) / scale);
+    dst[l] = (S)((double)get_elem(src, g.lo_rec(field), g.at(i, j, k)) / scale);
 }
 
 __device__ __forceinline__ double mat(const double *m, int nx, int ny, int i, int j, int k)
@@ -154,7 +154,8 @@ hipError_t launch_unpack(const Geom &g, int field, const T *src, S *dst, hipStre
     int X, Y, Z;
     extents(g, field, X, Y, Z);
     long long n = (long long)X * Y * Z;
-    hipLaunchKernelGGL((k_unpack<T, S>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, X, Y, n, src, dst, scale);
+    hipLaunchKernelGGL((k_unpack<T, S>), dim3(blocks_for(n)), dim3(kBlock), 0, s, g, field, X, Y, n, src, dst,
+                       scale);
     return hipGetLastError();
 }
 

@@ -74,14 +74,13 @@ __device__ __forceinline__ typename V2<T>::type ld2(const T *plane, unsigned bof
     return *(FDTD_GLOBAL const typename V2<T>::type *)(uni(plane) + boff);
 }
 
-// Two consecutive field cells of storage type S, widened to the compute type.
-// Compensated storage also reads the two residuals from lo_plane, the same
-// plane of the residual box (one byte per cell).
+// Two consecutive field cells of storage type S, widened to the compute type (plain
+// types; compensated cells are read as loaded bits with their group's residual records).
 template <typename S>
-__device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *plane, unsigned boff,
-                                                                       const char *lo_plane)
+__device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *plane, unsigned boff)
 {
     using C = typename Store<S>::C;
+    static_assert(!Store<S>::comp, "compensated cells are read by ldb and ldrec");
     if constexpr (sizeof(S) == 2) {
         const unsigned u = *(FDTD_GLOBAL const unsigned *)(uni(plane) + boff);
         const unsigned short ua = (unsigned short)(u & 0xffffu), ub = (unsigned short)(u >> 16);
@@ -89,19 +88,10 @@ __device__ __forceinline__ typename V2<typename Store<S>::C>::type ldf(const S *
         __builtin_memcpy(&a, &ua, 2);
         __builtin_memcpy(&b, &ub, 2);
         typename V2<C>::type r;
-        if constexpr (Store<S>::comp) {
-            const unsigned short q = *(FDTD_GLOBAL const unsigned short *)(uni(lo_plane) + boff / 2);
-            float x0, x1;
-            Store<S>::dec2(u, q, x0, x1);
-            r[0] = x0;
-            r[1] = x1;
-        } else {
-            r[0] = Store<S>::widen(a);
-            r[1] = Store<S>::widen(b);
-        }
+        r[0] = Store<S>::widen(a);
+        r[1] = Store<S>::widen(b);
         return r;
     } else {
-        (void)lo_plane;
         return *(FDTD_GLOBAL const typename V2<C>::type *)(uni(plane) + boff);
     }
 }
@@ -118,33 +108,48 @@ constexpr int kRawBufferWord3 = 0x00020000;  // gfx9 raw buffer: 32-bit data for
 constexpr int kStoreNT = 2;
 
 template <typename S, bool NT>
-__device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigned boff, char *lo_plane,
+__device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigned boff,
                                          const typename V2<typename Store<S>::C>::type &x)
 {
+    static_assert(!Store<S>::comp, "compensated cells are stored by st_group");
     constexpr int kPol = NT ? kStoreNT : 0;
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(plane, 0, (int)plane_bytes, kRawBufferWord3);
     if constexpr (sizeof(S) == 2) {
         // both cells rounded by one packed conversion
-        if constexpr (Store<S>::comp) {
-            unsigned hh;
-            unsigned short q;
-            Store<S>::enc2(x[0], x[1], hh, q);
-            __builtin_amdgcn_raw_buffer_store_b32(hh, r, boff, 0, kPol);
-            // residual box: one byte per cell, the same plane layout (a dropped offset stays dropped)
-            const __amdgpu_buffer_rsrc_t rq =
-                __builtin_amdgcn_make_buffer_rsrc(lo_plane, 0, (int)(plane_bytes / 2), kRawBufferWord3);
-            __builtin_amdgcn_raw_buffer_store_b16(q, rq, boff / 2, 0, kPol);
-        } else {
-            (void)lo_plane;
-            __builtin_amdgcn_raw_buffer_store_b32(Store<S>::pack2(x[0], x[1]), r, boff, 0, kPol);
-        }
+        __builtin_amdgcn_raw_buffer_store_b32(Store<S>::pack2(x[0], x[1]), r, boff, 0, kPol);
     } else if constexpr (sizeof(S) == 4) {
-        (void)lo_plane;
         __builtin_amdgcn_raw_buffer_store_b64(x, r, boff, 0, kPol);
     } else {
-        (void)lo_plane;
         __builtin_amdgcn_raw_buffer_store_b128(x, r, boff, 0, kPol);
     }
+}
+
+// Compensated storage: the two cells of the three components of a group (E or H), each
+// rounded to a 16-bit pair plus residual bytes, stored as three pairs and one pair of
+// residual records (rec_plane: the group's record plane, kRecBytes per cell, roff the
+// lanes' record offset; dropped offsets stay dropped).
+template <typename S, bool NT>
+__device__ __forceinline__ void st_group(S *const f[3], unsigned plane_bytes, unsigned boff, char *rec_plane,
+                                         unsigned roff, const typename V2<typename Store<S>::C>::type *x)
+{
+    static_assert(Store<S>::comp, "st_group stores compensated cells");
+    constexpr int kPol = NT ? kStoreNT : 0;
+    unsigned short q[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        unsigned hh;
+        Store<S>::enc2(x[c][0], x[c][1], hh, q[c]);
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(f[c], 0, (int)plane_bytes, kRawBufferWord3);
+        __builtin_amdgcn_raw_buffer_store_b32(hh, r, boff, 0, kPol);
+    }
+    // record of the first cell: the low residual bytes; of the second: the high ones
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    u2 w;
+    w.x = (unsigned)(q[0] & 0xffu) | ((unsigned)(q[1] & 0xffu) << 8) | ((unsigned)(q[2] & 0xffu) << 16);
+    w.y = (unsigned)(q[0] >> 8) | ((unsigned)(q[1] >> 8) << 8) | ((unsigned)(q[2] >> 8) << 16);
+    const __amdgpu_buffer_rsrc_t rr =
+        __builtin_amdgcn_make_buffer_rsrc(rec_plane, 0, (int)(plane_bytes / 2 * kRecBytes), kRawBufferWord3);
+    __builtin_amdgcn_raw_buffer_store_b64(w, rr, roff, 0, kPol);
 }
 
 // Buffer load of two field cells of storage type S (compute type out) with the plane as the
@@ -153,66 +158,69 @@ __device__ __forceinline__ void st_plane(S *plane, unsigned plane_bytes, unsigne
 // needs neither a branch nor registers cleared ahead of the loads.
 typedef unsigned RawPair __attribute__((ext_vector_type(2)));
 
-template <typename S, bool RAW = false>
-__device__ __forceinline__ typename V2<typename Store<S>::C>::type ldb(const S *plane, unsigned nrec, unsigned boff,
-                                                                       const char *lo_plane)
+template <typename S>
+__device__ __forceinline__ typename V2<typename Store<S>::C>::type ldb(const S *plane, unsigned nrec, unsigned boff)
 {
     using C = typename Store<S>::C;
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void *)plane, 0, (int)nrec, kRawBufferWord3);
     if constexpr (sizeof(S) == 2) {
         const unsigned u = __builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0);
-        const unsigned short ua = (unsigned short)(u & 0xffffu), ub = (unsigned short)(u >> 16);
-        S a, b;
-        __builtin_memcpy(&a, &ua, 2);
-        __builtin_memcpy(&b, &ub, 2);
-        typename V2<C>::type out;
         if constexpr (Store<S>::comp) {
-            // residual plane: one byte per cell (a dropped offset stays dropped at half)
-            const __amdgpu_buffer_rsrc_t rq =
-                __builtin_amdgcn_make_buffer_rsrc((void *)lo_plane, 0, (int)(nrec / 2), kRawBufferWord3);
-            const unsigned short q = __builtin_amdgcn_raw_buffer_load_b16(rq, boff / 2, 0, 0);
-            if constexpr (RAW) {
-                // the loaded bits as they are (decoded where they are first used, see dec_raw),
-                // carried as one 64-bit vector: a residual put into a float element on its own
-                // would be a denormal bit pattern, which the compiler may flush
-                RawPair raw;
-                raw.x = u;
-                raw.y = q;
-                return __builtin_bit_cast(typename V2<C>::type, raw);
-            } else {
-                float x0, x1;
-                Store<S>::dec2(u, q, x0, x1);
-                out[0] = x0;
-                out[1] = x1;
-            }
+            // the loaded bits as they are (decoded with the group's residual records where they
+            // are first used, see dec_group), carried in an integer vector: a 16-bit pair put into a
+            // float element on its own may be a denormal bit pattern, which the compiler may flush
+            RawPair raw;
+            raw.x = u;
+            raw.y = 0u;
+            return __builtin_bit_cast(typename V2<C>::type, raw);
         } else {
+            const unsigned short ua = (unsigned short)(u & 0xffffu), ub = (unsigned short)(u >> 16);
+            S a, b;
+            __builtin_memcpy(&a, &ua, 2);
+            __builtin_memcpy(&b, &ub, 2);
+            typename V2<C>::type out;
             out[0] = Store<S>::widen(a);
             out[1] = Store<S>::widen(b);
+            return out;
         }
-        return out;
     } else if constexpr (sizeof(S) == 4) {
-        (void)lo_plane;
-        typedef unsigned u2 __attribute__((ext_vector_type(2)));
         return __builtin_bit_cast(typename V2<C>::type, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
     } else {
-        (void)lo_plane;
-        typedef unsigned u4 __attribute__((ext_vector_type(4)));
         return __builtin_bit_cast(typename V2<C>::type, __builtin_amdgcn_raw_buffer_load_b128(r, boff, 0, 0));
     }
 }
 
-// Decodes, in place, two compensated cells loaded by ldb<S, true> (no-op for other types):
-// the decode waits for the load, so it runs where the values are first needed, a plane
-// after the prefetch, not where the load is issued.
+// The residual records of a lane's two cells (compensated storage): one 64-bit load from the
+// group's record plane (nrec 0: zeros; a dropped offset reads zeros), as loaded bits.
+__device__ __forceinline__ V2<float>::type ldrec(const char *rec_plane, unsigned nrec, unsigned roff)
+{
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void *)rec_plane, 0, (int)nrec,
+                                                                       kRawBufferWord3);
+    return __builtin_bit_cast(V2<float>::type, __builtin_amdgcn_raw_buffer_load_b64(r, roff, 0, 0));
+}
+
+// Decodes, in place, the three components of a compensated group loaded by ldb (16-bit pairs)
+// and ldrec (records; no-op for other types): the decode waits for the loads, so it runs
+// where the values are first needed, a plane after the prefetch, not where the loads issue.
 template <typename S>
-__device__ __forceinline__ void dec_raw(typename V2<typename Store<S>::C>::type &v)
+__device__ __forceinline__ void dec_group(typename V2<typename Store<S>::C>::type *v,
+                                          const typename V2<typename Store<S>::C>::type &rec)
 {
     if constexpr (Store<S>::comp) {
-        const RawPair raw = __builtin_bit_cast(RawPair, v);
+        const RawPair w = __builtin_bit_cast(RawPair, rec);
         float x0, x1;
-        Store<S>::dec2(raw.x, raw.y, x0, x1);
-        v[0] = x0;
-        v[1] = x1;
+        Store<S>::template dec2r<0>(__builtin_bit_cast(RawPair, v[0]).x, w.x, w.y, x0, x1);
+        v[0][0] = x0;
+        v[0][1] = x1;
+        Store<S>::template dec2r<1>(__builtin_bit_cast(RawPair, v[1]).x, w.x, w.y, x0, x1);
+        v[1][0] = x0;
+        v[1][1] = x1;
+        Store<S>::template dec2r<2>(__builtin_bit_cast(RawPair, v[2]).x, w.x, w.y, x0, x1);
+        v[2][0] = x0;
+        v[2][1] = x1;
+    } else {
+        (void)v;
+        (void)rec;
     }
 }
 
@@ -295,10 +303,9 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     const int lr = row + 1;     // LDS row
     const int lc = HX + c0;     // LDS column of the first cell
 
-    // residual plane of a compensated box (a field pointer points at element 0; the residual
-    // box holds one byte per element, lo_off bytes past it)
-    auto lp = [&](const S *base, long long pk) { return (const char *)base + g.lo_off + pk; };
-    auto lq = [&](S *base, long long pk) { return (char *)base + g.lo_off + pk; };
+    // residual record plane of a compensated group (base: Ex or Hx, whose element 0 is lo_off
+    // bytes before the group's record of element 0; kRecBytes per element)
+    auto rp = [&](const S *base, long long pk) { return (const char *)base + g.lo_off + kRecBytes * pk; };
     const S *Ex = src.f[0], *Ey = src.f[1], *Ez = src.f[2];
     const S *Hx = src.f[3], *Hy = src.f[4], *Hz = src.f[5];
     const vec zero = (vec)(T)0;
@@ -321,8 +328,11 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     constexpr bool RING = !CH_ARR && !Store<S>::comp;
     constexpr int U = RING ? M : 1;  // planes per loop iteration
     vec RE[M][3], RH[M][3], RC[M][3], RK[M][3];
+    vec RRE[M], RRH[M];  // compensated storage: residual records of the E and H groups (loaded bits)
 #pragma unroll
     for (int r = 0; r < M; ++r) {
+        RRE[r] = zero;
+        RRH[r] = zero;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             RE[r][q] = zero;
@@ -343,17 +353,28 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     // first planes of stage 1, in the phase-0 slots
     if (act) {
         const long long pk = (long long)k0 * P;
-        RE[ES(0, 0)][0] = ldf(Ex + pk, offs, lp(Ex, pk));
-        RE[ES(0, 0)][1] = ldf(Ey + pk, offs, lp(Ey, pk));
-        RE[ES(0, 0)][2] = ldf(Ez + pk, offs, lp(Ez, pk));
+        if constexpr (Store<S>::comp) {
+            RE[ES(0, 0)][0] = ldb<S>(Ex + pk, plane_bytes, offs);
+            RE[ES(0, 0)][1] = ldb<S>(Ey + pk, plane_bytes, offs);
+            RE[ES(0, 0)][2] = ldb<S>(Ez + pk, plane_bytes, offs);
+            dec_group<S>(RE[ES(0, 0)], ldrec(rp(Ex, pk), cplane_bytes, offc));
+        } else {
+            RE[ES(0, 0)][0] = ldf(Ex + pk, offs);
+            RE[ES(0, 0)][1] = ldf(Ey + pk, offs);
+            RE[ES(0, 0)][2] = ldf(Ez + pk, offs);
+        }
         // E(k0+1) and H(k0) as loaded bits: the first plane decodes them like every prefetch
         const unsigned n1 = k0 + 1 < nz ? plane_bytes : 0u;
-        RE[ES(-1, 0)][0] = ldb<S, true>(Ex + pk + P, n1, offs, lp(Ex, pk + P));
-        RE[ES(-1, 0)][1] = ldb<S, true>(Ey + pk + P, n1, offs, lp(Ey, pk + P));
-        RE[ES(-1, 0)][2] = ldb<S, true>(Ez + pk + P, n1, offs, lp(Ez, pk + P));
-        RH[HS(0, 0)][0] = ldb<S, true>(Hx + pk, plane_bytes, offs, lp(Hx, pk));
-        RH[HS(0, 0)][1] = ldb<S, true>(Hy + pk, plane_bytes, offs, lp(Hy, pk));
-        RH[HS(0, 0)][2] = ldb<S, true>(Hz + pk, plane_bytes, offs, lp(Hz, pk));
+        RE[ES(-1, 0)][0] = ldb<S>(Ex + pk + P, n1, offs);
+        RE[ES(-1, 0)][1] = ldb<S>(Ey + pk + P, n1, offs);
+        RE[ES(-1, 0)][2] = ldb<S>(Ez + pk + P, n1, offs);
+        RH[HS(0, 0)][0] = ldb<S>(Hx + pk, plane_bytes, offs);
+        RH[HS(0, 0)][1] = ldb<S>(Hy + pk, plane_bytes, offs);
+        RH[HS(0, 0)][2] = ldb<S>(Hz + pk, plane_bytes, offs);
+        if constexpr (Store<S>::comp) {
+            RRE[ES(-1, 0)] = ldrec(rp(Ex, pk + P), n1 ? cplane_bytes : 0u, offc);
+            RRH[HS(0, 0)] = ldrec(rp(Hx, pk), cplane_bytes, offc);
+        }
         if (CE_ARR) {
             RC[HS(0, 0)][0] = ld2(c.ce[0] + pk, offc);
             RC[HS(0, 0)][1] = ld2(c.ce[1] + pk, offc);
@@ -378,13 +399,13 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
             const int k = kk + u;
             if (k > kend)
                 break;
-            // residual planes: their bases are formed per plane from the field bases (a
-            // loop-invariant copy per field would hold 24 more SGPRs)
+            // residual record planes: their bases are formed per plane from the group bases (a
+            // loop-invariant copy would hold more SGPRs)
             long long lo = g.lo_off;
             if constexpr (Store<S>::comp)
                 __asm__ volatile("" : "+s"(lo));
-            auto lp = [&](const S *base, long long pk) { return (const char *)base + lo + pk; };
-            auto lq = [&](S *base, long long pk) { return (char *)base + lo + pk; };
+            auto rp = [&](const S *base, long long pk) { return (const char *)base + lo + kRecBytes * pk; };
+            auto rq = [&](S *base, long long pk) { return (char *)base + lo + kRecBytes * pk; };
             // ---------------- prefetch stage-1 inputs of plane k+1 (E of k+2) ----------------
             // (planes past the chunk or the domain, and lanes outside it, read zeros)
             {
@@ -393,26 +414,27 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                 const long long pk1 = pv ? (long long)(k + 1) * P : 0;
                 const long long pk2 = pv2 ? pk1 + P : 0;
                 const unsigned n1 = pv ? plane_bytes : 0u, n2 = pv2 ? plane_bytes : 0u, nc = pv ? cplane_bytes : 0u;
-                RE[ES(-2, ph)][0] = ldb<S, true>(Ex + pk2, n2, lfo, lp(Ex, pk2));
-                RE[ES(-2, ph)][1] = ldb<S, true>(Ey + pk2, n2, lfo, lp(Ey, pk2));
-                RE[ES(-2, ph)][2] = ldb<S, true>(Ez + pk2, n2, lfo, lp(Ez, pk2));
-                RH[HS(-1, ph)][0] = ldb<S, true>(Hx + pk1, n1, lfo, lp(Hx, pk1));
-                RH[HS(-1, ph)][1] = ldb<S, true>(Hy + pk1, n1, lfo, lp(Hy, pk1));
-                RH[HS(-1, ph)][2] = ldb<S, true>(Hz + pk1, n1, lfo, lp(Hz, pk1));
+                RE[ES(-2, ph)][0] = ldb<S>(Ex + pk2, n2, lfo);
+                RE[ES(-2, ph)][1] = ldb<S>(Ey + pk2, n2, lfo);
+                RE[ES(-2, ph)][2] = ldb<S>(Ez + pk2, n2, lfo);
+                RH[HS(-1, ph)][0] = ldb<S>(Hx + pk1, n1, lfo);
+                RH[HS(-1, ph)][1] = ldb<S>(Hy + pk1, n1, lfo);
+                RH[HS(-1, ph)][2] = ldb<S>(Hz + pk1, n1, lfo);
+                if constexpr (Store<S>::comp) {
+                    RRE[ES(-2, ph)] = ldrec(rp(Ex, pk2), n2 ? cplane_bytes : 0u, lco);
+                    RRH[HS(-1, ph)] = ldrec(rp(Hx, pk1), nc, lco);
+                }
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     if (CE_ARR)
-                        RC[HS(-1, ph)][q] = ldb<T>(c.ce[q] + pk1, nc, lco, nullptr);
+                        RC[HS(-1, ph)][q] = ldb<T>(c.ce[q] + pk1, nc, lco);
                     if (CH_ARR)
-                        RK[HS(-1, ph)][q] = ldb<T>(c.ch[q] + pk1, nc, lco, nullptr);
+                        RK[HS(-1, ph)][q] = ldb<T>(c.ch[q] + pk1, nc, lco);
                 }
             }
             // compensated types: the previous plane's prefetch, decoded now (E role -1, H role 0)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                dec_raw<S>(RE[ES(-1, ph)][q]);
-                dec_raw<S>(RH[HS(0, ph)][q]);
-            }
+            dec_group<S>(RE[ES(-1, ph)], RRE[ES(-1, ph)]);
+            dec_group<S>(RH[HS(0, ph)], RRH[HS(0, ph)]);
             // ---------------- stage the E input of every stage ----------------
             if (lane_ok) {
 #pragma unroll
@@ -469,12 +491,20 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                         const bool wr = livep && own && pp >= kb;
                         const unsigned so = wr ? offs : kDrop;
                         const long long pk = (long long)(pp > 0 ? pp : 0) * P;
-                        st_plane<S, NT>(dst.f[0] + pk, plane_bytes, so, lq(dst.f[0], pk), E[0]);
-                        st_plane<S, NT>(dst.f[1] + pk, plane_bytes, so, lq(dst.f[1], pk), E[1]);
-                        st_plane<S, NT>(dst.f[2] + pk, plane_bytes, so, lq(dst.f[2], pk), E[2]);
-                        st_plane<S, NT>(dst.f[3] + pk, plane_bytes, so, lq(dst.f[3], pk), Hn[0]);
-                        st_plane<S, NT>(dst.f[4] + pk, plane_bytes, so, lq(dst.f[4], pk), Hn[1]);
-                        st_plane<S, NT>(dst.f[5] + pk, plane_bytes, so, lq(dst.f[5], pk), Hn[2]);
+                        if constexpr (Store<S>::comp) {
+                            const unsigned sor = wr ? offc : kDrop;  // record offset
+                            S *const fe[3] = {dst.f[0] + pk, dst.f[1] + pk, dst.f[2] + pk};
+                            S *const fh[3] = {dst.f[3] + pk, dst.f[4] + pk, dst.f[5] + pk};
+                            st_group<S, NT>(fe, plane_bytes, so, rq(dst.f[0], pk), sor, E);
+                            st_group<S, NT>(fh, plane_bytes, so, rq(dst.f[3], pk), sor, Hn);
+                        } else {
+                            st_plane<S, NT>(dst.f[0] + pk, plane_bytes, so, E[0]);
+                            st_plane<S, NT>(dst.f[1] + pk, plane_bytes, so, E[1]);
+                            st_plane<S, NT>(dst.f[2] + pk, plane_bytes, so, E[2]);
+                            st_plane<S, NT>(dst.f[3] + pk, plane_bytes, so, Hn[0]);
+                            st_plane<S, NT>(dst.f[4] + pk, plane_bytes, so, Hn[1]);
+                            st_plane<S, NT>(dst.f[5] + pk, plane_bytes, so, Hn[2]);
+                        }
                     }
                 }
                 if (s == TS)
@@ -526,6 +556,12 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                         RH[r][q] = RH[r - 1][q];
                         RC[r][q] = RC[r - 1][q];
                         RK[r][q] = RK[r - 1][q];
+                    }
+                if constexpr (Store<S>::comp)
+#pragma unroll
+                    for (int r = M - 1; r > 0; --r) {
+                        RRE[r] = RRE[r - 1];
+                        RRH[r] = RRH[r - 1];
                     }
             }
         }

@@ -78,9 +78,10 @@ __device__ inline unsigned pack2_bf16(float a, float b)
     return u;
 }
 
-// Compensated 16-bit storage: the 16-bit value (array of these) plus, in a
-// parallel int8 box, its rounding residual in units of 1/256 of the 16-bit
-// ulp. Three bytes per value; decoding is exact in FP32.
+// Compensated 16-bit storage: the 16-bit value (array of these) plus its rounding
+// residual, an int8 in units of 1/256 of the 16-bit ulp, kept in a record with
+// the residuals of the node's other two E (or H) components (kRecBytes below).
+// Decoding is exact in FP32.
 struct f16c {
     _Float16 h;
 };
@@ -230,6 +231,27 @@ __device__ inline float sbyte1_f32(unsigned q)
     return r;
 }
 
+__device__ inline float sbyte2_f32(unsigned q)
+{
+    float r;
+    __asm__("v_cvt_f32_i32_sdwa %0, sext(%1) dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_2"
+            : "=v"(r)
+            : "v"(q));
+    return r;
+}
+
+// Signed byte B (0..2) of a word as FP32.
+template <int B>
+__device__ inline float sbyte_f32(unsigned q)
+{
+    if constexpr (B == 0)
+        return sbyte0_f32(q);
+    else if constexpr (B == 1)
+        return sbyte1_f32(q);
+    else
+        return sbyte2_f32(q);
+}
+
 // FP32 powers of two whose exponent fields are the two halves of f (each < 256).
 __device__ inline void pair_pow2(pk_u16x2 f, float &lo, float &hi)
 {
@@ -289,6 +311,20 @@ struct Store<f16c> {
         a = (float)ha + sbyte0_f32(q) * sa;
         b = (float)hb + sbyte1_f32(q) * sb;
     }
+    // the same from the residual records of the two cells (w0: cell a, w1: cell b), component B
+    template <int B>
+    __device__ static void dec2r(unsigned u, unsigned w0, unsigned w1, float &a, float &b)
+    {
+        const pk_u16x2 e = __builtin_elementwise_max(pair_exp(u, 10, 0x1f), (pk_u16x2)(unsigned short)1);
+        float sa, sb;
+        pair_pow2(e + (pk_u16x2)(unsigned short)94, sa, sb);
+        const unsigned short ua = (unsigned short)(u & 0xffffu), ub = (unsigned short)(u >> 16);
+        _Float16 ha, hb;
+        __builtin_memcpy(&ha, &ua, 2);
+        __builtin_memcpy(&hb, &ub, 2);
+        a = (float)ha + sbyte_f32<B>(w0) * sa;
+        b = (float)hb + sbyte_f32<B>(w1) * sb;
+    }
 };
 
 template <>
@@ -325,29 +361,43 @@ struct Store<bf16c> {
         a = bits_f32(u << 16) + sbyte0_f32(q) * sa;
         b = bits_f32(u & 0xffff0000u) + sbyte1_f32(q) * sb;
     }
+    template <int B>
+    __device__ static void dec2r(unsigned u, unsigned w0, unsigned w1, float &a, float &b)
+    {
+        const pk_u16x2 e = __builtin_elementwise_max(pair_exp(u, 7, 0xff), (pk_u16x2)(unsigned short)16);
+        float sa, sb;
+        pair_pow2(e - (pk_u16x2)(unsigned short)15, sa, sb);
+        a = bits_f32(u << 16) + sbyte_f32<B>(w0) * sa;
+        b = bits_f32(u & 0xffff0000u) + sbyte_f32<B>(w1) * sb;
+    }
 };
 
-// Element access through the storage rules. lo_off: byte distance from a
-// compensated box's element 0 to its residual box's element 0 (unused for
-// the plain types).
+// Compensated storage keeps the residuals of the three E (or H) components of a node
+// together in one 4-byte record (byte c: component c, byte 3 zero), so that a sweep
+// reads a lane's residuals with one load per group instead of one per component.
+constexpr int kRecBytes = 4;
+
+// Element access through the storage rules. lo: byte distance from a compensated
+// box's element 0 to the byte of its component in the residual record of element 0
+// (records kRecBytes apart; unused for the plain types).
 template <typename T>
-__host__ __device__ inline typename Store<T>::C get_elem(const T *a, long long lo_off, long long o)
+__host__ __device__ inline typename Store<T>::C get_elem(const T *a, long long lo, long long o)
 {
     if constexpr (Store<T>::comp)
-        return Store<T>::dec(a[o], ((const signed char *)a + lo_off)[o]);
+        return Store<T>::dec(a[o], ((const signed char *)a + lo)[kRecBytes * o]);
     else
         return Store<T>::widen(a[o]);
 }
 
 template <typename T>
-__host__ __device__ inline void put_elem(T *a, long long lo_off, long long o, typename Store<T>::C v)
+__host__ __device__ inline void put_elem(T *a, long long lo, long long o, typename Store<T>::C v)
 {
     if constexpr (Store<T>::comp) {
         T h;
         signed char q;
         Store<T>::enc(v, h, q);
         a[o] = h;
-        ((signed char *)a + lo_off)[o] = q;
+        ((signed char *)a + lo)[kRecBytes * o] = q;
     } else {
         a[o] = Store<T>::narrow(v);
     }

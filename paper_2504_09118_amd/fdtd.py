@@ -244,7 +244,8 @@ class Solver:
 
     storage: "f32" (default), "f64" (test-only double-precision fields),
     "f16" / "bf16" (16-bit fields computed in FP32, rounded once per sweep), or
-    "f16c" / "bf16c" (16-bit value plus an int8 residual: compensated, 3 bytes).
+    "f16c" / "bf16c" (16-bit value plus an int8 residual: compensated; the three
+    residuals of a node's E, or H, components share a 4-byte record).
     kernel: "auto", "plain", "fused", "slab" or "temporal"; tb_steps: steps
     per sweep for "temporal", 1..4 (0: 4 for FP32 fields without per-node Ch,
     else 3).
