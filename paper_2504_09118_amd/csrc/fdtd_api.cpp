@@ -653,10 +653,11 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     }
     h->tvariant = env_int("FDTD_TEMPORAL_VARIANT", 0);
     if (kern == FDTD_KERNEL_TEMPORAL && o->tb_steps == 0)
-        // default steps per sweep: 4 for FP32 fields (512^3: 258 Gcell/s against 226 at 3);
-        // 3 where a fourth stage costs more than it saves (16-bit storage: its conversions;
-        // per-node Ch: a third coefficient pipeline spills registers)
-        h->tb = o->storage == FDTD_F32 && !h->ch_arr && h->tvariant == 0 ? 4 : 3;
+        // default steps per sweep: 4 for FP32 fields (512^3: 258 Gcell/s against 226 at 3) and
+        // compensated storage (244 against 220: its codec work is per sweep); 3 where a fourth
+        // stage costs more than it saves (plain 16-bit storage: 270 against 320, its register
+        // rings spill; per-node Ch: a third coefficient pipeline spills registers)
+        h->tb = (o->storage == FDTD_F32 || is_comp(o->storage)) && !h->ch_arr && h->tvariant == 0 ? 4 : 3;
     if (h->tb > 3)
         h->tvariant = 0;  // one row per wave is built for 1..3 steps per sweep
     h->tzchunk = env_int("FDTD_TZCHUNKS", 0);

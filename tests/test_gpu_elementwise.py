@@ -103,9 +103,10 @@ SPANS = {"f16": (-26, 14), "f16c": (-26, 14), "bf16": (-120, 14), "bf16c": (-120
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16", "f16c", "bf16c"])
-@pytest.mark.parametrize("steps,wide_span", [(3, False), (5, False), (3, True)])
-def test_16bit_sweeps_equal_the_storage_model(storage, steps, wide_span):
-    """16-bit storage: one sweep of 3 steps (and a second, remainder sweep of 2) from a
+@pytest.mark.parametrize("steps,tb,wide_span", [(3, 3, False), (5, 3, False), (3, 3, True), (4, 4, False),
+                                                (7, 4, True)])
+def test_16bit_sweeps_equal_the_storage_model(storage, steps, tb, wide_span):
+    """16-bit storage: one sweep of tb = 3 or 4 steps (and a second, remainder sweep) from a
     16-bit state, node by node against the model that rounds the FP32 state once per sweep.
     The model is exact (FMA included), so every node must be equal; the report also gives
     the largest difference in storage steps (one 16-bit ulp, or one residual step for the
@@ -115,14 +116,14 @@ def test_16bit_sweeps_equal_the_storage_model(storage, steps, wide_span):
     nx, ny, nz = DIMS
     store = steps_of_storage(storage)
     eps, e, h, start, ce, ch = model_inputs(nx, ny, nz, 43, store, SPANS[storage] if wide_span else None)
-    with Solver(nx, ny, nz, 1.0, S, eps_r=eps, storage=storage, kernel="temporal", tb_steps=3) as s:
+    with Solver(nx, ny, nz, 1.0, S, eps_r=eps, storage=storage, kernel="temporal", tb_steps=tb) as s:
         s.set_fields(e, h)
         s.step(steps)
-        assert s.query()["sweeps"] == (1 if steps == 3 else 2)
+        assert s.query()["sweeps"] == (1 if steps == tb else 2)
         got = s.get_fields(np.float32)
     # the initial state on the device is the model's start
     model = [a.copy() for a in start]
-    fp32_fma.run_sweeps(model, ce, ch, steps, 3, store=store)
+    fp32_fma.run_sweeps(model, ce, ch, steps, tb, store=store)
     total, bad, worst = 0, 0, 0.0
     for name, g, m in zip(("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"), got, model):
         diff = np.abs(g.astype(np.float64) - m.astype(np.float64))
@@ -133,6 +134,6 @@ def test_16bit_sweeps_equal_the_storage_model(storage, steps, wide_span):
         total += g.size
         bad += int(np.sum(diff > 0))
         worst = max(worst, float(np.max(diff / unit)))
-    print(f"\n{storage}, {steps} steps: {bad} of {total} nodes differ from the storage model; "
+    print(f"\n{storage}, {steps} steps, tb {tb}: {bad} of {total} nodes differ from the storage model; "
           f"largest difference {worst:.3g} storage steps")
     assert bad == 0, f"{bad} nodes differ (largest {worst:.3g} storage steps)"

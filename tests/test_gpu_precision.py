@@ -99,6 +99,9 @@ CASES = [
     # 101 = 33 x 3 + 2: the last sweep is a 2-step remainder sweep (one rounding)
     ((32, 32, 32), 101, 3, "f16", 2e-3),
     ((32, 32, 32), 101, 3, "bf16c", 1e-4),
+    # the compensated default, 4 steps per sweep (101 = 25 x 4 + 1)
+    ((32, 32, 32), 100, 4, "f16c", 1e-5),
+    ((32, 32, 32), 101, 4, "bf16c", 1e-4),
 ]
 
 
