@@ -113,7 +113,7 @@ typedef struct {
                            FDTD_F16C, FDTD_BF16C (16-bit based storage runs the temporal kernel only) */
     int kernel;         /* fdtd_kernel, default FDTD_KERNEL_AUTO */
     int tb_steps;       /* steps per sweep for FDTD_KERNEL_TEMPORAL, 1..4 (0: library default:
-                           4 for FP32 and compensated fields without per-node Ch, else 3) */
+                           4 without per-node Ch, else 3) */
     int device;         /* HIP device ordinal, default 0 */
     void *stream;       /* hipStream_t to enqueue on; NULL: the library creates its own */
     void *arena;        /* caller-owned device memory for all device state; NULL: hipMalloc */

@@ -653,11 +653,10 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
     }
     h->tvariant = env_int("FDTD_TEMPORAL_VARIANT", 0);
     if (kern == FDTD_KERNEL_TEMPORAL && o->tb_steps == 0)
-        // default steps per sweep: 4 for FP32 fields (512^3: 258 Gcell/s against 226 at 3) and
-        // compensated storage (244 against 220: its codec work is per sweep); 3 where a fourth
-        // stage costs more than it saves (plain 16-bit storage: 270 against 320, its register
-        // rings spill; per-node Ch: a third coefficient pipeline spills registers)
-        h->tb = (o->storage == FDTD_F32 || is_comp(o->storage)) && !h->ch_arr && h->tvariant == 0 ? 4 : 3;
+        // default steps per sweep: 4 (512^3: FP32 258 Gcell/s against 226 at 3, 16-bit storage
+        // 329-333 against 320-322, compensated 244-245 against 220-224); 3 with per-node Ch,
+        // whose third coefficient pipeline spills registers at 4
+        h->tb = o->storage != FDTD_F64 && !h->ch_arr && h->tvariant == 0 ? 4 : 3;
     if (h->tb > 3)
         h->tvariant = 0;  // one row per wave is built for 1..3 steps per sweep
     h->tzchunk = env_int("FDTD_TZCHUNKS", 0);

@@ -321,11 +321,11 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     // Role r of a ring sits in slot (r + off + ph) mod M; the next plane has phase ph - 1, so
     // role r becomes role r + 1 in place. Stage s's H one plane down, which its E update reads,
     // is role s+1 of the H ring before stage s+1 updates it.
-    // The kernels with per-node Ch and the compensated types do not unroll (their M copies
-    // spill registers): they run the ring at phase 0 and rotate it by one slot after each
-    // plane, a copy of each live value, as the rename would.
+    // The kernels with per-node Ch, the compensated types and plain 16-bit storage at TS = 4
+    // do not unroll (their M copies spill registers): they run the ring at phase 0 and rotate
+    // it by one slot after each plane, a copy of each live value, as the rename would.
     constexpr int M = TS + 2;
-    constexpr bool RING = !CH_ARR && !Store<S>::comp;
+    constexpr bool RING = !CH_ARR && !Store<S>::comp && !(sizeof(S) == 2 && TS == 4);
     constexpr int U = RING ? M : 1;  // planes per loop iteration
     vec RE[M][3], RH[M][3], RC[M][3], RK[M][3];
     vec RRE[M], RRH[M];  // compensated storage: residual records of the E and H groups (loaded bits)

@@ -247,8 +247,7 @@ class Solver:
     "f16c" / "bf16c" (16-bit value plus an int8 residual: compensated; the three
     residuals of a node's E, or H, components share a 4-byte record).
     kernel: "auto", "plain", "fused", "slab" or "temporal"; tb_steps: steps
-    per sweep for "temporal", 1..4 (0: 4 for FP32 and compensated fields
-    without per-node Ch, else 3).
+    per sweep for "temporal", 1..4 (0: 4 without per-node Ch, else 3).
     stream: a hipStream_t handle (int), a torch.cuda.Stream, or "torch" for
     torch's current stream; None lets the library create its own stream.
     arena: "torch" to allocate all device state as one torch uint8 tensor

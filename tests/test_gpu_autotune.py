@@ -50,7 +50,7 @@ def test_autotune_keeps_state_and_bits(storage):
         for key in ("kernel", "tb_steps", "variant", "zchunks"):
             assert chosen[key] == fastest[key]
         if storage == "f16":
-            assert all(t["kernel"] == "temporal" and t["tb_steps"] == 3 for t in tried)
+            assert all(t["kernel"] == "temporal" and t["tb_steps"] == 4 for t in tried)
         if storage == "f64":
             assert all(t["kernel"] != "temporal" for t in tried)
         print(f"\n{storage}: {len(tried)} schedules, chosen {chosen}")
