@@ -29,15 +29,14 @@
 //   - a z-chunk starts TS planes early and ends TS-1 planes late so every
 //     stage sees exact inputs on the planes it stores.
 //   - by default one workgroup per CU takes tile numbers from a counter in
-//     the solver's arena (the kernels with per-node Ch: one workgroup per
-//     tile, numbered for the XCDs); the tile order never changes the bits.
+//     the solver's arena; the tile order never changes the bits.
 // Walls and the region outside the domain need no per-node predicate: a
 // wall-normal H sees a curl of wall-tangential E (+0, stored as +0, with -0
 // wall-normal H stored as +0), H outside the domain sees only zeros and stays 0,
 // and with per-node Ce arrays (0 on the walls and, as initial value and load
-// result, outside the domain) a wall or outside E gets E + 0 * curl = E. The
-// scalar-Ce E update keeps its wall predicates, and the kernels with per-node
-// Ch keep all of them (the predicate-free form spills registers there).
+// result, outside the domain) a wall or outside E gets E + 0 * curl = E; per-node
+// Ch arrays are 0 outside the domain in the same way. The scalar-Ce E update
+// keeps its wall predicates.
 // Only the last stage stores, only own cells. Arithmetic per node is
 // curl_update with the operand order of every other schedule: TS sweeps of
 // this kernel equal TS single steps bit for bit.
@@ -253,9 +252,9 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
     constexpr int LP = HX + W + HX + V;     // LDS row pitch (one pad vector at the end)
     constexpr int RB = R + 2;               // LDS rows (one pad row each side)
     using vec = typename V2<T>::type;
-    // predicate-free updates (see the file header); the kernels with per-node Ch keep the
-    // predicates: without them their register allocation spills
-    constexpr bool NP_H = !CH_ARR, NP_E = CE_ARR && !CH_ARR;
+    // predicate-free E update with per-node Ce arrays (see the file header; the H update
+    // never needs one)
+    constexpr bool NP_E = CE_ARR;
     __shared__ __attribute__((aligned(16))) T sE[TS][3][RB][LP];  // E input of each stage, plane p_s
     __shared__ __attribute__((aligned(16))) T sH[2][3][RB][LP];   // H of the current stage (alternating)
 
@@ -518,24 +517,18 @@ __device__ __forceinline__ void temporal_tile(const Geom &g, const Fields<S> &sr
                 const vec *Ks = RK[HS(s, ph)];
                 vec *H = RH[HS(s, ph)];
                 const int hb = (s + 1) & 1;
-                if (live && (NP_H || act)) {
+                if (live) {
                     const vec ezj = *(const vec *)&sE[s][2][lr + 1][lc];  // Ez(i, j+1)
                     const vec exj = *(const vec *)&sE[s][0][lr + 1][lc];  // Ex(i, j+1)
                     const T ezr = sE[s][2][lr][lc + V];                    // Ez(ib+V, j)
                     const T eyr = sE[s][1][lr][lc + V];                    // Ey(ib+V, j)
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
-                        const int i = ib + v;
-                        if (!NP_H && i >= nx)
-                            continue;
                         const T ez_ip = v + 1 < V ? Es[2][v + 1] : ezr;
                         const T ey_ip = v + 1 < V ? Es[1][v + 1] : eyr;
-                        if (NP_H || i >= 1)
-                            H[0][v] = curl_update(H[0][v], Ks[0][v], en[1][v], Es[1][v], ezj[v], Es[2][v]);
-                        if (NP_H || j >= 1)
-                            H[1][v] = curl_update(H[1][v], Ks[1][v], ez_ip, Es[2][v], en[0][v], Es[0][v]);
-                        if (NP_H || p >= 1)
-                            H[2][v] = curl_update(H[2][v], Ks[2][v], exj[v], Es[0][v], ey_ip, Es[1][v]);
+                        H[0][v] = curl_update(H[0][v], Ks[0][v], en[1][v], Es[1][v], ezj[v], Es[2][v]);
+                        H[1][v] = curl_update(H[1][v], Ks[1][v], ez_ip, Es[2][v], en[0][v], Es[0][v]);
+                        H[2][v] = curl_update(H[2][v], Ks[2][v], exj[v], Es[0][v], ey_ip, Es[1][v]);
                     }
                 }
                 if (lane_ok) {
@@ -745,12 +738,16 @@ hipError_t launch_ts(const Geom &g, const Fields<T> &src, const Fields<T> &dst,
     const int cpx = cus_per_xcd();
     dim3 block(64, 16);
     const bool cea = c.ce[0] != nullptr, cha = c.ch[0] != nullptr;
-    // the queue form of the kernels with per-node Ch spills registers: they keep one
-    // workgroup per tile
-    if (queue && !cha && temporal_sched() == 1) {
+    if (queue && temporal_sched() == 1) {
         const int nvb = (ntiles + kXcds - 1) / kXcds * kXcds;
         dim3 grid(std::min(ntiles, kXcds * cpx));  // one workgroup per CU
-        if (cea)
+        if (cea && cha)
+            hipLaunchKernelGGL((k_temporal_q<T, TS, RPW, true, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk,
+                               ntx, nty, ntiles, nvb, cpx, queue);
+        else if (cha)
+            hipLaunchKernelGGL((k_temporal_q<T, TS, RPW, false, true, NT>), grid, block, 0, s, g, src, dst, c, kchunk,
+                               ntx, nty, ntiles, nvb, cpx, queue);
+        else if (cea)
             hipLaunchKernelGGL((k_temporal_q<T, TS, RPW, true, false, NT>), grid, block, 0, s, g, src, dst, c, kchunk,
                                ntx, nty, ntiles, nvb, cpx, queue);
         else
