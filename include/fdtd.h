@@ -170,7 +170,7 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
  * contiguous tile range, which the slab sweeps treat as 1),
  * FDTD_TEMPORAL_SCHED = 0 / 1 (temporal sweeps, read once per process: one
  * workgroup per tile in the FDTD_XCD_REMAP order; default 1, one workgroup per
- * CU taking tiles from a queue, except with per-node Ch).
+ * CU taking tiles from a queue).
  */
 int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *coef,
                 const fdtd_opts *opts, fdtd_t *out);

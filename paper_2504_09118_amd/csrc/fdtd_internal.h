@@ -245,8 +245,9 @@ int xcd_remap();
 int cus_per_xcd();
 
 // How the temporal sweeps hand out tiles: 0 one workgroup per tile, in the
-// FDTD_XCD_REMAP order; 1 (the default; not for the kernels with per-node Ch)
-// one workgroup per CU taking tiles from a queue. FDTD_TEMPORAL_SCHED selects it.
+// FDTD_XCD_REMAP order; 1 (the default) one workgroup per CU taking tiles from a
+// queue (the batched serving sweeps with per-node Ch: one workgroup per tile).
+// FDTD_TEMPORAL_SCHED selects it.
 int temporal_sched();
 
 // Set the thread-local message fdtd_last_error returns.
