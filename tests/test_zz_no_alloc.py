@@ -66,11 +66,12 @@ def test_noalloc_steps_equal_fdtd_step_on_two_calls_second_smaller(tb):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16c"])
-def test_noalloc_16bit_storage(storage):
-    a, b = _pair(70, 45, 29, 11, storage=storage)
+@pytest.mark.parametrize("tb", [3, 4])
+def test_noalloc_16bit_storage(storage, tb):
+    a, b = _pair(70, 45, 29, 11, storage=storage, tb=tb)
     try:
-        _noalloc(a, 8)
-        b.step(8)
+        _noalloc(a, 9)          # 3 + 3 + 3, or 4 + 4 and a 1-step remainder
+        b.step(9)
         _same(a, b, storage)
     finally:
         a.close()
