@@ -81,6 +81,20 @@ def test_every_schedule_gives_the_same_bits():
                 assert np.array_equal(x, y), t
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f16c", "bf16c"])
+def test_default_steps_per_sweep(storage):
+    """The temporal default: 4 steps per sweep, 3 with per-node Ch (whose fourth stage spills)."""
+    P = _P()
+    n = 24
+    mu = ci.sphere_eps(n, n, n, seed=6, nspheres=2)
+    with P.Solver(n, n, n, 1.0, S, storage=storage) as s:
+        assert s.schedule["kernel"] == "temporal" and s.schedule["tb_steps"] == 4
+    with P.Solver(n, n, n, 1.0, S, mu_r=mu, storage=storage) as s:
+        assert s.schedule["tb_steps"] == 3
+    with P.Solver(n, n, n, 1.0, S, storage=storage, kernel="temporal", tb_steps=2) as s:
+        assert s.schedule["tb_steps"] == 2
+
+
 def test_set_schedule_validation():
     P = _P()
     with P.Solver(16, 16, 16, 1.0, S, storage="f16") as s:
