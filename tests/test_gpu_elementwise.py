@@ -36,7 +36,7 @@ def wide(fields, draw, lo, hi):
     return out
 
 
-def model_inputs(nx, ny, nz, seed, store, span=None):
+def model_inputs(nx, ny, nz, seed, store, span=None, mu=None):
     eps = ci.sphere_eps(nx, ny, nz, seed=33, nspheres=6)
     e = ci.random_e(nx, ny, nz, seed=seed, dtype=np.float32)
     h = ci.random_h(nx, ny, nz, seed=seed + 1, dtype=np.float32)
@@ -46,7 +46,7 @@ def model_inputs(nx, ny, nz, seed, store, span=None):
     start = oracle.make_state([store(a).astype(np.float64) for a in e], [store(a).astype(np.float64) for a in h])
     start = [a.astype(np.float32) for a in start]
     ce = [a.astype(np.float32) for a in oracle.round_to(oracle.coef_e(nx, ny, nz, 1.0, S, eps), np.float32)]
-    ch = [a.astype(np.float32) for a in oracle.round_to(oracle.coef_h(nx, ny, nz, 1.0, S), np.float32)]
+    ch = [a.astype(np.float32) for a in oracle.round_to(oracle.coef_h(nx, ny, nz, 1.0, S, mu), np.float32)]
     return eps, e, h, start, ce, ch
 
 
@@ -111,12 +111,25 @@ def test_16bit_sweeps_equal_the_storage_model(storage, steps, tb, wide_span):
     The model is exact (FMA included), so every node must be equal; the report also gives
     the largest difference in storage steps (one 16-bit ulp, or one residual step for the
     compensated types). Measured: 0 differing nodes of 2.08e6 for all four types."""
+    compare_16bit_sweeps(storage, steps, tb, wide_span, None)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16c"])
+@pytest.mark.parametrize("steps,tb", [(3, 3), (5, 3), (4, 4)])
+def test_16bit_sweeps_with_per_node_ch_equal_the_storage_model(storage, steps, tb):
+    """The same with per-node Ch arrays (mu_r in [1, 1.5] per cell): the kernels with a third
+    coefficient pipeline, 3 steps per sweep by default, 4 allowed."""
+    nx, ny, nz = DIMS
+    compare_16bit_sweeps(storage, steps, tb, False, ci.uniform_cell_eps(nx, ny, nz, seed=12, lo=1.0, hi=1.5))
+
+
+def compare_16bit_sweeps(storage, steps, tb, wide_span, mu):
     from paper_2504_09118_amd import Solver
 
     nx, ny, nz = DIMS
     store = steps_of_storage(storage)
-    eps, e, h, start, ce, ch = model_inputs(nx, ny, nz, 43, store, SPANS[storage] if wide_span else None)
-    with Solver(nx, ny, nz, 1.0, S, eps_r=eps, storage=storage, kernel="temporal", tb_steps=tb) as s:
+    eps, e, h, start, ce, ch = model_inputs(nx, ny, nz, 43, store, SPANS[storage] if wide_span else None, mu)
+    with Solver(nx, ny, nz, 1.0, S, eps_r=eps, mu_r=mu, storage=storage, kernel="temporal", tb_steps=tb) as s:
         s.set_fields(e, h)
         s.step(steps)
         assert s.query()["sweeps"] == (1 if steps == tb else 2)
@@ -134,6 +147,7 @@ def test_16bit_sweeps_equal_the_storage_model(storage, steps, tb, wide_span):
         total += g.size
         bad += int(np.sum(diff > 0))
         worst = max(worst, float(np.max(diff / unit)))
-    print(f"\n{storage}, {steps} steps, tb {tb}: {bad} of {total} nodes differ from the storage model; "
+    print(f"\n{storage}, {steps} steps, tb {tb}{', per-node Ch' if mu is not None else ''}: {bad} of {total} nodes "
+          f"differ from the storage model; "
           f"largest difference {worst:.3g} storage steps")
     assert bad == 0, f"{bad} nodes differ (largest {worst:.3g} storage steps)"
