@@ -151,7 +151,9 @@ int fdtd_required_bytes(int nx, int ny, int nz, const fdtd_coef *coef, const fdt
  * and time step dt, and enqueue the coefficient precompute on its stream.
  * Fields start at zero.
  * Checks: nx, ny, nz >= 2; nx*ny*nz <= 2^33; one padded x-y plane
- * (round_up(nx+1, 64) * (ny+1) values) below 2^31 bytes (FDTD_E_ARG);
+ * (round_up(nx+1, 64) * (ny+1) values, of 8 bytes for FP64 storage and 4
+ * bytes otherwise: 16-bit storage sweeps FP32 coefficient planes and 4-byte
+ * residual-record planes of the same size) below 2^31 bytes (FDTD_E_ARG);
  * dx, dt finite and > 0; every material value
  * finite and > 0; the Courant limit dt*sqrt(3)/dx < sqrt(min eps_r * min mu_r)
  * (FDTD_E_CFL); a given arena of at least fdtd_required_bytes, and without

@@ -547,9 +547,11 @@ int fdtd_create(int nx, int ny, int nz, double dx, double dt, const fdtd_coef *c
         return fail(FDTD_E_ARG, "tb_steps must be 1..4 (0: the default), got %d", o->tb_steps);
     {
         // the sweeps address one padded x-y plane with 32-bit byte offsets and mark a dropped
-        // access with an offset of 2^31, so a plane must stay below 2^31 bytes
+        // access with an offset of 2^31, so a plane must stay below 2^31 bytes; with 16-bit
+        // storage the same sweep addresses planes of FP32 coefficients and of 4-byte residual
+        // records, so the bound applies to 4-byte elements there too
         const long long px = ((long long)nx + 1 + 63) / 64 * 64;
-        const long long esz = o->storage == FDTD_F64 ? 8 : o->storage == FDTD_F32 ? 4 : 2;
+        const long long esz = o->storage == FDTD_F64 ? 8 : 4;
         if (px * (ny + 1) * esz >= (1LL << 31))
             return fail(FDTD_E_ARG, "x-y plane of %lld bytes: planes must stay below 2^31 bytes",
                         px * (ny + 1) * esz);

@@ -31,13 +31,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-def _create(nx=8, ny=8, nz=8, dx=1.0, dt=0.25, eps=None, mu=None, kernel=0):
+def _create(nx=8, ny=8, nz=8, dx=1.0, dt=0.25, eps=None, mu=None, kernel=0, storage=F.F32):
     lib = F.load_library()
     coef = F._Coef(eps_r=eps.ctypes.data if eps is not None else None,
                    mu_r=mu.ctypes.data if mu is not None else None)
     opts = F._Opts()
     lib.fdtd_opts_default(ctypes.byref(opts))
     opts.kernel = kernel
+    opts.storage = storage
     h = ctypes.c_void_p(None)
     st = lib.fdtd_create(nx, ny, nz, dx, dt, ctypes.byref(coef), ctypes.byref(opts), ctypes.byref(h))
     return st, h
@@ -237,6 +238,16 @@ def test_create_rejects_oversized_planes():
     # 24000 x 24000 cells, 2 planes deep: few enough cells, but one padded FP32 x-y plane
     # (24064 x 24001 x 4 B) reaches 2^31 bytes
     st, h = _create(24000, 24000, 2)
+    assert st == F.E_ARG and not h.value
+    assert b"plane" in F.load_library().fdtd_last_error()
+
+
+@pytest.mark.parametrize("storage", [F.F16, F.BF16, F.F16C, F.BF16C])
+def test_create_rejects_16bit_planes_whose_coefficient_planes_reach_2_31_bytes(storage):
+    # 23200 x 23200 cells: a padded 16-bit field plane (23232 x 23201 x 2 B) stays below 2^31
+    # bytes, but the FP32 coefficient plane and the 4-byte residual-record plane the same sweep
+    # addresses with 32-bit offsets would not
+    st, h = _create(23200, 23200, 2, storage=storage)
     assert st == F.E_ARG and not h.value
     assert b"plane" in F.load_library().fdtd_last_error()
 
