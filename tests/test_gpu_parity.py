@@ -189,6 +189,23 @@ def test_temporal_parity_ragged(tb):
         assert np.array_equal(a.astype(np.float32), b.astype(np.float32))
 
 
+@pytest.mark.parametrize("tb", [1, 2, 3, 4])
+def test_temporal_per_node_ch_with_scalar_ce(tb):
+    # per-node Ch (mu_r array) with a scalar Ce (no eps_r): the temporal kernels whose E update
+    # keeps its wall predicates; 23 steps leave a remainder sweep for tb = 2, 3 and 4
+    nx, ny, nz, steps = 97, 45, 33, 23
+    mu = ci.uniform_cell_eps(nx, ny, nz, seed=21, lo=1.0, hi=1.5)
+    e = ci.random_e(nx, ny, nz, seed=22, dtype=np.float32)
+    h = ci.random_h(nx, ny, nz, seed=23, dtype=np.float32)
+    got = run_gpu(nx, ny, nz, e, h, None, mu, steps, kernel="temporal", tb_steps=tb)
+    plain = run_gpu(nx, ny, nz, e, h, None, mu, steps, kernel="plain")
+    for a, b in zip(got, plain):
+        assert np.array_equal(a, b)
+    assert oracle.tangential_max(got) == 0.0
+    err = rel_l2(got, oracle_reference(nx, ny, nz, e, h, None, mu, steps))
+    assert err < 1e-5
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_resume_is_bitwise(kernel):
     nx, ny, nz, n = 40, 24, 20, 37
