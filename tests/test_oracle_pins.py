@@ -247,6 +247,10 @@ def test_splitmix64_published_sequence():
     # first outputs of SplitMix64 seeded with 0 (the published generator's stream)
     out = ci.splitmix64(0, np.arange(3, dtype=np.uint64))
     assert int(out[0]) == 0xE220A8397B1DCDAF
+    # the reference sequence commonly published for seed 1234567
+    assert [int(x) for x in ci.splitmix64(1234567, np.arange(5, dtype=np.uint64))] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431,
+        16408922859458223821]
     # counter form agrees with a plain sequential Python implementation
     def seq(seed, n):
         m = (1 << 64) - 1
