@@ -93,6 +93,9 @@ def main() -> int:
     ap.add_argument("--numpy-steps", type=int, default=1, help="NumPy slicing-form steps per precision")
     ap.add_argument("--autotune", action="store_true", help="time every built schedule first and keep the fastest")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--settle-ms", type=float, default=100.0,
+                    help="sweeps of the same schedule on a twin cavity right before the warm-up steps, "
+                         "for about this many ms (0: none)")
     ap.add_argument("--no-other-schedule", action="store_true",
                     help="skip timing the 3-step sweep beside the 4-step default")
     ap.add_argument("--serving-requests", type=int, default=200)
@@ -138,10 +141,11 @@ def main() -> int:
     q = s.query()
     kernel = q["kernel"]
     steps_per_launch = int(q["steps_per_sweep"])
-    # the serving leg and then the bandwidth probe run before the warm-up steps: after an idle
-    # spell the GPU's clocks take about 20 ms of full load to settle (the first ~10 sweeps run
-    # up to 20 % slow); the probe's 42 back-to-back copies (about 34 ms) are such a load, right
-    # before the warm-up (the serving leg, at 0.9 of its saturation, leaves the GPU idle at times)
+    # the serving leg and the bandwidth probe run before the warm-up steps, then the settle
+    # sweeps: after an idle spell, or a memory-bound load like the probe's copies, the stencil's
+    # first sweeps run slow (clocks settling), so the same schedule sweeps a twin cavity back to
+    # back right before the warm-up (the serving leg, at 0.9 of its saturation, leaves the GPU
+    # idle at times)
     serving = None
     if not args.no_serving:
         from paper_2504_09118_amd import serve
@@ -150,6 +154,7 @@ def main() -> int:
                                     n_requests=args.serving_requests, stream=stream,
                                     log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
     probe = copy_probe(stream)
+    twin, settle_info = settle(s, nx, ny, nz, dx, dt, eps, mu, e, args.storage, stream, args.settle_ms)
     s.step(args.warmup)
     s.sync()
     torch.cuda.synchronize()
@@ -183,6 +188,8 @@ def main() -> int:
     s_sched = s.schedule
     d = s.diag()
     s.close()
+    if twin is not None:
+        twin.close()
     other = None
     if kernel == "temporal" and steps_per_launch == 4 and args.tb_steps == 0 and not args.no_other_schedule:
         other = other_schedule(nx, ny, nz, dx, dt, eps, mu, e, args.storage, stream, 3, max(3, args.steps // 3 * 3))
@@ -261,6 +268,8 @@ def main() -> int:
             other["traffic_frac"] = round(tr / 1e9 / (other["avg_launch_ms"] / 1e3) / HBM_PEAK_GBS, 4)
         result["other_schedule"] = other
     result["copy_probe"] = probe
+    if settle_info is not None:
+        result["settle"] = settle_info
     if serving is not None:
         result["serving"] = serving
     if not args.no_cpu_baseline:
@@ -294,6 +303,36 @@ def other_schedule(nx, ny, nz, dx, dt, eps, mu, e, storage, stream, tb, steps):
     return {"kernel": "temporal", "steps_per_launch": tb, "steps": n_calls * tb,
             "gcells": round(nx * ny * nz * n_calls * tb / (ms / 1e3) / 1e9, 3),
             "avg_launch_ms": round(ms / n_calls, 5)}
+
+
+def settle(s, nx, ny, nz, dx, dt, eps, mu, e, storage, stream, ms_target):
+    """Clock settling right before the warm-up steps: the measured solver's schedule on a twin
+    cavity (same inputs, its own state), swept back to back for about ms_target ms and enqueued
+    on the same stream ahead of the warm-up, so the GPU runs the stencil without a gap into the
+    warm-up and timed steps. The measured solver's state and steps are untouched. Returns the
+    twin (closed after the timed region, so no free runs before it) and what was run."""
+    import torch
+
+    from paper_2504_09118_amd import Solver
+
+    if ms_target <= 0:
+        return None, None
+    sc = s.schedule
+    twin = Solver(nx, ny, nz, dx, dt, eps_r=eps, mu_r=mu, storage=storage, stream=stream)
+    twin.set_schedule(sc["kernel"], sc["tb_steps"], sc["variant"], sc["zchunks"])
+    twin.set_fields(e)
+    per = sc["tb_steps"] if sc["kernel"] == "temporal" else 1
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    twin.step(2 * per)  # a first estimate of the sweep time
+    b.record(stream)
+    torch.cuda.synchronize()
+    est = max(a.elapsed_time(b) / 2, 1e-3)
+    n = max(1, math.ceil((ms_target - 2 * est) / est))
+    twin.step(n * per)
+    return twin, {"kind": "twin cavity, same schedule", "steps": (n + 2) * per,
+                  "est_ms": round((n + 2) * est, 2)}
 
 
 def copy_probe(stream, nbytes: int = 2 << 30, reps: int = 40):

@@ -5,6 +5,7 @@
 - The roofline object follows from the dominant kernel's average launch time
   (algorithmic bytes per launch over that time), and the 3-step comparison
   sweep carries the same fields.
+- The settle sweeps on a twin cavity are reported (`settle`).
 - `--gpus` above 1 exits with status 2 and a message before touching the GPU
   (a CPU test).
 """
@@ -58,6 +59,9 @@ def test_bench_line_contract_small_cavity():
     assert rf["frac"] == pytest.approx(rf["achieved"] / rf["peak"], abs=1e-4)
     assert d["config"]["steps_per_launch"] == 4 and rf["launches_timed"] == steps // 4
     assert rf["traffic"] is None  # counters are recorded for the 512^3 cavity only
+    # the settle sweeps ran on a twin cavity with the same schedule, before the warm-up steps
+    st = d["settle"]
+    assert st["kind"].startswith("twin cavity") and st["steps"] > 0 and st["steps"] % 4 == 0
     other = d["other_schedule"]
     assert other["steps_per_launch"] == 3 and other["gcells"] > 0
     assert other["frac"] == pytest.approx(60 * cells / 1e9 / (other["avg_launch_ms"] / 1e3) / 8000.0, abs=1e-4)
