@@ -314,11 +314,17 @@ def settle(s, nx, ny, nz, dx, dt, eps, mu, e, storage, stream, ms_target):
     import torch
 
     from paper_2504_09118_amd import Solver
+    from paper_2504_09118_amd.fdtd import E_NOMEM, FdtdError
 
     if ms_target <= 0:
         return None, None
     sc = s.schedule
-    twin = Solver(nx, ny, nz, dx, dt, eps_r=eps, mu_r=mu, storage=storage, stream=stream)
+    try:
+        twin = Solver(nx, ny, nz, dx, dt, eps_r=eps, mu_r=mu, storage=storage, stream=stream)
+    except FdtdError as err:
+        if err.status != E_NOMEM:
+            raise
+        return None, {"kind": "none: no HBM left for a twin cavity"}
     twin.set_schedule(sc["kernel"], sc["tb_steps"], sc["variant"], sc["zchunks"])
     twin.set_fields(e)
     per = sc["tb_steps"] if sc["kernel"] == "temporal" else 1
