@@ -330,15 +330,26 @@ def settle(s, nx, ny, nz, dx, dt, eps, mu, e, storage, stream, ms_target):
     per = sc["tb_steps"] if sc["kernel"] == "temporal" else 1
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    twin.step(2 * per)  # a first estimate of the sweep time
-    b.record(stream)
-    torch.cuda.synchronize()
-    est = max(a.elapsed_time(b) / 2, 1e-3)
-    n = max(1, math.ceil((ms_target - 2 * est) / est))
-    twin.step(n * per)
-    return twin, {"kind": "twin cavity, same schedule", "steps": (n + 2) * per,
-                  "est_ms": round((n + 2) * est, 2)}
+    # timed batches of doubling size until half the target has run (the first sweeps after the
+    # twin's set-up are slow, so the sweep time is taken from the latest batch), then the rest
+    # in one batch left running into the warm-up
+    done_ms, steps, k = 0.0, 0, 2
+    while True:
+        a.record(stream)
+        twin.step(k * per)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        done_ms, steps = done_ms + ms, steps + k * per
+        est = max(ms / k, 1e-3)
+        if done_ms >= ms_target / 2 or k >= 64:
+            break
+        k *= 2
+    n = max(0, math.ceil((ms_target - done_ms) / est))
+    if n:
+        twin.step(n * per)
+    return twin, {"kind": "twin cavity, same schedule", "steps": steps + n * per,
+                  "est_ms": round(done_ms + n * est, 2)}
 
 
 def copy_probe(stream, nbytes: int = 2 << 30, reps: int = 40):
