@@ -143,9 +143,9 @@ def main() -> int:
     steps_per_launch = int(q["steps_per_sweep"])
     # the serving leg and the bandwidth probe run before the warm-up steps, then the settle
     # sweeps: after an idle spell, or a memory-bound load like the probe's copies, the stencil's
-    # first sweeps run slow (clocks settling), so the same schedule sweeps a twin cavity back to
-    # back right before the warm-up (the serving leg, at 0.9 of its saturation, leaves the GPU
-    # idle at times)
+    # first sweeps run slow (clocks settling), so the same schedule sweeps a twin cavity right
+    # before the warm-up (the serving leg, at 0.9 of its saturation, leaves the GPU idle at
+    # times)
     serving = None
     if not args.no_serving:
         from paper_2504_09118_amd import serve
@@ -307,10 +307,11 @@ def other_schedule(nx, ny, nz, dx, dt, eps, mu, e, storage, stream, tb, steps):
 
 def settle(s, nx, ny, nz, dx, dt, eps, mu, e, storage, stream, ms_target):
     """Clock settling right before the warm-up steps: the measured solver's schedule on a twin
-    cavity (same inputs, its own state), swept back to back for about ms_target ms and enqueued
-    on the same stream ahead of the warm-up, so the GPU runs the stencil without a gap into the
-    warm-up and timed steps. The measured solver's state and steps are untouched. Returns the
-    twin (closed after the timed region, so no free runs before it) and what was run."""
+    cavity (same inputs, its own state), swept for about ms_target ms on the same stream, the
+    last batch still running when the warm-up is enqueued, so the GPU runs the stencil without
+    a gap into the warm-up and timed steps. The measured solver's state and steps are
+    untouched. Returns the twin (closed after the timed region, so no free runs before it) and
+    what was run; no twin when the HBM has no room for one."""
     import torch
 
     from paper_2504_09118_amd import Solver
