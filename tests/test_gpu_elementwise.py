@@ -123,10 +123,22 @@ def test_16bit_sweeps_with_per_node_ch_equal_the_storage_model(storage, steps, t
     compare_16bit_sweeps(storage, steps, tb, False, ci.uniform_cell_eps(nx, ny, nz, seed=12, lo=1.0, hi=1.5))
 
 
-def compare_16bit_sweeps(storage, steps, tb, wide_span, mu):
+# the smallest grids the boundary accepts (two cells on an axis) and one- or two-cell slabs
+DEGENERATE_DIMS = [(2, 2, 2), (2, 3, 65), (65, 2, 2), (3, 67, 2), (129, 2, 3)]
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16", "f16c", "bf16c"])
+@pytest.mark.parametrize("dims", DEGENERATE_DIMS)
+def test_16bit_sweeps_on_degenerate_grids_equal_the_storage_model(storage, dims):
+    """The same on degenerate grids: a 4-step sweep and a 3-step remainder sweep, where most
+    lanes of a tile lie outside the domain and most nodes are wall nodes."""
+    compare_16bit_sweeps(storage, 7, 4, False, None, dims)
+
+
+def compare_16bit_sweeps(storage, steps, tb, wide_span, mu, dims=DIMS):
     from paper_2504_09118_amd import Solver
 
-    nx, ny, nz = DIMS
+    nx, ny, nz = dims
     store = steps_of_storage(storage)
     eps, e, h, start, ce, ch = model_inputs(nx, ny, nz, 43, store, SPANS[storage] if wide_span else None, mu)
     with Solver(nx, ny, nz, 1.0, S, eps_r=eps, mu_r=mu, storage=storage, kernel="temporal", tb_steps=tb) as s:
@@ -147,7 +159,8 @@ def compare_16bit_sweeps(storage, steps, tb, wide_span, mu):
         total += g.size
         bad += int(np.sum(diff > 0))
         worst = max(worst, float(np.max(diff / unit)))
-    print(f"\n{storage}, {steps} steps, tb {tb}{', per-node Ch' if mu is not None else ''}: {bad} of {total} nodes "
+    print(f"\n{nx}x{ny}x{nz} {storage}, {steps} steps, tb {tb}{', per-node Ch' if mu is not None else ''}: "
+          f"{bad} of {total} nodes "
           f"differ from the storage model; "
           f"largest difference {worst:.3g} storage steps")
     assert bad == 0, f"{bad} nodes differ (largest {worst:.3g} storage steps)"
